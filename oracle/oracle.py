@@ -1,0 +1,254 @@
+"""ctypes wrapper of the FP64 CPU oracle (slfo).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The oracle shares no code with the
+HIP library and never loads it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "slfo.c")
+_OUT_DIR = os.path.join(_HERE, "_build")
+_LIB = os.path.join(_OUT_DIR, "libslfo.so")
+_lib = None
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(_OUT_DIR, exist_ok=True)
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-Wall", "-Wextra", "-Wno-unused-parameter", _SRC, "-o", tmp, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("d_min", ctypes.c_double), ("d_max", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("jitter", ctypes.c_int32), ("tssd_T", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("alpha", ctypes.c_double), ("eta", ctypes.c_double),
+                ("occ_tol", ctypes.c_double), ("kernel_step", ctypes.c_int32),
+                ("kernel_radius_init", ctypes.c_int32), ("term_mask", ctypes.c_uint32),
+                ("energy_mode", ctypes.c_int32)]
+
+
+class _Rig(ctypes.Structure):
+    _fields_ = [("n_views", ctypes.c_int32)] + [(n, ctypes.c_void_p) for n in (
+        "width", "height", "grid_w", "grid_h", "K", "R", "t", "rgb", "labels", "pix_off", "nbr_off", "nbr")]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.slfo_create.argtypes = [ctypes.POINTER(_Rig), ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_int)]
+        L.slfo_create.restype = P
+        L.slfo_destroy.argtypes = [P]
+        L.slfo_destroy.restype = None
+        L.slfo_set_params.argtypes = [P, ctypes.POINTER(_Params)]
+        L.slfo_set_threads.argtypes = [I]
+        L.slfo_set_threads.restype = None
+        L.slfo_sp_offset.argtypes = [P, I]
+        L.slfo_sp_offset.restype = ctypes.c_int64
+        L.slfo_sp_total.argtypes = [P]
+        L.slfo_sp_total.restype = ctypes.c_int64
+        L.slfo_sp_stats.argtypes = [P, P, P, P]
+        L.slfo_mix64.argtypes = [ctypes.c_uint64]
+        L.slfo_mix64.restype = ctypes.c_uint64
+        L.slfo_level_q.argtypes = [P, I, I, I]
+        L.slfo_level_q.restype = D
+        L.slfo_kernel_radius.argtypes = [P, I, I]
+        L.slfo_homography.argtypes = [P, I, I, P, D, P]
+        L.slfo_sweep_cost_plane.argtypes = [P, I, I, P]
+        L.slfo_sweep_cost_plane.restype = D
+        L.slfo_sweep_sp.argtypes = [P, I, I, P, P, P, P]
+        L.slfo_sweep_all.argtypes = [P, P, P, P, P]
+        L.slfo_energy.argtypes = [P, P, I, I, P]
+        L.slfo_energy.restype = D
+        L.slfo_refine_sp.argtypes = [P, P, I, I, I, P, P, P, P]
+        L.slfo_refine_all.argtypes = [P, P, I, P, P, P, P]
+        L.slfo_refine_trace.argtypes = [P, P, I, I, I, P, P, P, I]
+        L.slfo_render_depth.argtypes = [P, P, I, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def mix64(z: int) -> int:
+    return int(lib().slfo_mix64(ctypes.c_uint64(z & 0xFFFFFFFFFFFFFFFF)))
+
+
+def set_threads(n: int) -> None:
+    lib().slfo_set_threads(int(n))
+
+
+def make_params(mp) -> _Params:
+    g = mp if isinstance(mp, dict) else mp.as_dict()
+    return _Params(int(g["levels"]), float(g["d_min"]), float(g["d_max"]), int(g["seed"]) & (2**64 - 1),
+                   int(g["jitter"]), float(g["tssd_T"]), float(g["sigma"]), float(g["alpha"]), float(g["eta"]),
+                   float(g["occ_tol"]), int(g["kernel_step"]), int(g["kernel_radius_init"]),
+                   int(g["term_mask"]), int(g["energy_mode"]))
+
+
+class Oracle:
+    """FP64 oracle bound to one rig.  Planes are float64 arrays [S_total, 4] = (d, nx, ny, nz)."""
+
+    def __init__(self, rig, params):
+        self._L = lib()
+        views = rig.views
+        V = len(views)
+        self.V = V
+        self._keep = []
+        W = np.array([v.W for v in views], np.int32)
+        H = np.array([v.H for v in views], np.int32)
+        gw = np.array([v.gw for v in views], np.int32)
+        gh = np.array([v.gh for v in views], np.int32)
+        K = np.ascontiguousarray(np.stack([np.asarray(v.K, np.float64).reshape(9) for v in views]))
+        R = np.ascontiguousarray(np.stack([np.asarray(v.R, np.float64).reshape(9) for v in views]))
+        t = np.ascontiguousarray(np.stack([np.asarray(v.t, np.float64).reshape(3) for v in views]))
+        rgb = np.ascontiguousarray(np.concatenate([np.asarray(v.rgb, np.uint8).reshape(-1) for v in views]))
+        labels = np.ascontiguousarray(np.concatenate([np.asarray(v.labels, np.int32).reshape(-1) for v in views]))
+        pix_off = np.zeros(V + 1, np.int64)
+        pix_off[1:] = np.cumsum(W.astype(np.int64) * H)
+        nl = rig.neighbor_lists()
+        nbr_off = np.zeros(V + 1, np.int32)
+        nbr_off[1:] = np.cumsum([len(n) for n in nl])
+        nbr = np.array([x for n in nl for x in n] or [0], np.int32)
+        self._keep = [W, H, gw, gh, K, R, t, rgb, labels, pix_off, nbr_off, nbr]
+        self._rig = _Rig(V, *[_p(a) for a in self._keep])
+        self._params = make_params(params)
+        err = ctypes.c_int(0)
+        self._c = self._L.slfo_create(ctypes.byref(self._rig), ctypes.byref(self._params), ctypes.byref(err))
+        if not self._c:
+            raise ValueError("slfo_create failed: %d" % err.value)
+        self.S = int(self._L.slfo_sp_total(self._c))
+        self.sp_off = np.array([self._L.slfo_sp_offset(self._c, v) for v in range(V)] + [self.S], np.int64)
+        self.dims = [(int(v.W), int(v.H)) for v in views]
+
+    def __del__(self):
+        c = getattr(self, "_c", None)
+        if c:
+            self._L.slfo_destroy(c)
+            self._c = None
+
+    def set_params(self, params):
+        self._params = make_params(params)
+        rc = self._L.slfo_set_params(self._c, ctypes.byref(self._params))
+        if rc:
+            raise ValueError("bad params")
+
+    # -- statistics
+    def sp_stats(self):
+        area = np.empty(self.S, np.int32)
+        cen = np.empty((self.S, 2))
+        col = np.empty((self.S, 3))
+        self._L.slfo_sp_stats(self._c, _p(area), _p(cen), _p(col))
+        return area, cen, col
+
+    def level_q(self, view, sp, k):
+        return float(self._L.slfo_level_q(self._c, view, sp, k))
+
+    def kernel_radius(self, view, it):
+        return int(self._L.slfo_kernel_radius(self._c, view, it))
+
+    def homography(self, r, i, n, delta):
+        n = np.ascontiguousarray(n, np.float64)
+        H = np.empty(9)
+        if self._L.slfo_homography(self._c, r, i, _p(n), float(delta), _p(H)):
+            raise ValueError("bad views")
+        return H.reshape(3, 3)
+
+    # -- sweep
+    def sweep_cost(self, view, sp, plane):
+        pl = np.ascontiguousarray(plane, np.float64)
+        return float(self._L.slfo_sweep_cost_plane(self._c, view, sp, _p(pl)))
+
+    def sweep_sp(self, view, sp):
+        pl = np.empty(4)
+        cost = ctypes.c_double()
+        ch = ctypes.c_int32()
+        mg = ctypes.c_double()
+        if self._L.slfo_sweep_sp(self._c, view, sp, _p(pl), ctypes.byref(cost), ctypes.byref(ch), ctypes.byref(mg)):
+            raise ValueError("bad superpixel")
+        return pl, cost.value, ch.value, mg.value
+
+    def sweep(self):
+        planes = np.empty((self.S, 4))
+        cost = np.empty(self.S)
+        ch = np.empty(self.S, np.int32)
+        mg = np.empty(self.S)
+        if self._L.slfo_sweep_all(self._c, _p(planes), _p(cost), _p(ch), _p(mg)):
+            raise RuntimeError("sweep failed")
+        return planes, cost, ch, mg
+
+    # -- refinement
+    def energy(self, A, view, sp, plane):
+        A = np.ascontiguousarray(A, np.float64)
+        pl = np.ascontiguousarray(plane, np.float64)
+        return float(self._L.slfo_energy(self._c, _p(A), view, sp, _p(pl)))
+
+    def refine_sp(self, A, it, view, sp):
+        A = np.ascontiguousarray(A, np.float64)
+        pl = np.empty(4)
+        e = ctypes.c_double()
+        ch = ctypes.c_int32()
+        mg = ctypes.c_double()
+        if self._L.slfo_refine_sp(self._c, _p(A), it, view, sp, _p(pl), ctypes.byref(e), ctypes.byref(ch),
+                                  ctypes.byref(mg)):
+            raise ValueError("bad superpixel")
+        return pl, e.value, ch.value, mg.value
+
+    def refine(self, A, it):
+        A = np.ascontiguousarray(A, np.float64)
+        B = np.empty((self.S, 4))
+        e = np.empty(self.S)
+        ch = np.empty(self.S, np.int32)
+        mg = np.empty(self.S)
+        if self._L.slfo_refine_all(self._c, _p(A), it, _p(B), _p(e), _p(ch), _p(mg)):
+            raise RuntimeError("refine failed")
+        return B, e, ch, mg
+
+    def refine_trace(self, A, it, view, sp, cap=256):
+        A = np.ascontiguousarray(A, np.float64)
+        slots = np.empty(cap, np.int32)
+        planes = np.empty((cap, 4))
+        en = np.empty(cap)
+        n = self._L.slfo_refine_trace(self._c, _p(A), it, view, sp, _p(slots), _p(planes), _p(en), cap)
+        if n < 0:
+            raise ValueError("bad superpixel")
+        return slots[:n], planes[:n], en[:n]
+
+    def render_depth(self, planes, view):
+        planes = np.ascontiguousarray(planes, np.float64)
+        W, H = self.dims[view]
+        out = np.empty((H, W))
+        self._L.slfo_render_depth(self._c, _p(planes), view, _p(out))
+        return out
+
+    # -- convenience
+    def view_slice(self, view):
+        return slice(int(self.sp_off[view]), int(self.sp_off[view + 1]))
+
+    def run(self, iterations):
+        """Sweep then `iterations` refinement steps; returns the list of states and outputs."""
+        A, cost, ch, mg = self.sweep()
+        hist = [(A, cost, ch, mg)]
+        for it in range(1, iterations + 1):
+            B, e, c2, m2 = self.refine(A, it)
+            hist.append((B, e, c2, m2))
+            A = B
+        return hist
