@@ -4,7 +4,7 @@
               3 tilted rectangles, SLIC grid 20x15, 64 levels on [2, 8], 3 iterations.
 2  full HD:   8 toed-in cameras on an arc (radius 5, chord 1.5), f = 2400,
               1920x1080, background + 20 rectangles of which 6 low-texture,
-              grid 103x58, 256 levels on [1.9, 8.5], 8 iterations.
+              grid 103x58, 256 levels on [1.9, 8.6] (camera z of the scene spans 2.0-8.56 on the arc), 8 iterations.
 3  precision: 4x4 planar grid (spacing 0.05), f = 1600, 1280x720, the full-HD
               scene recipe, grid 84x47, 192 levels on [2, 8], 6 iterations.
 4  batched:   32 independent rigs; rig j (seed 400 + j) has U{3..16} views on
@@ -75,7 +75,7 @@ def config2(seed: int = 2, labels: str = "slic") -> Workload:
     scene = make_scene(rng, f=f, W=W, H=H, sp_px=347.0, n_rect=20, n_low=6)
     rig = build_rig(views, scene, 103, 58, name="fullhd-8arc-1920x1080", seed=seed, labels=labels)
     return Workload("fullhd-8arc-1920x1080", rig,
-                    MethodParams(levels=256, d_min=1.9, d_max=8.5, iterations=8))
+                    MethodParams(levels=256, d_min=1.9, d_max=8.6, iterations=8))
 
 
 def config3(seed: int = 3) -> Workload:

@@ -79,6 +79,7 @@ def lib():
         L.slfo_refine_sp.argtypes = [P, P, I, I, I, P, P, P, P]
         L.slfo_refine_all.argtypes = [P, P, I, P, P, P, P]
         L.slfo_refine_trace.argtypes = [P, P, I, I, I, P, P, P, I]
+        L.slfo_refine_pivot.argtypes = [P, P, I, I, I, I, P, P, P, P, P, P, I]
         L.slfo_render_depth.argtypes = [P, P, I, P]
         _lib = L
     return _lib
@@ -231,6 +232,22 @@ class Oracle:
         if n < 0:
             raise ValueError("bad superpixel")
         return slots[:n], planes[:n], en[:n]
+
+    def refine_pivot(self, A, it, view, sp, pivot_slot, cap=1024):
+        """Refinement of one superpixel with the propagation stage resolved toward
+        pivot_slot.  Returns (plane, energy, choice, trace_slots, trace_planes, trace_energies)."""
+        A = np.ascontiguousarray(A, np.float64)
+        pl = np.empty(4)
+        e = ctypes.c_double()
+        ch = ctypes.c_int32()
+        slots = np.empty(cap, np.int32)
+        planes = np.empty((cap, 4))
+        en = np.empty(cap)
+        n = self._L.slfo_refine_pivot(self._c, _p(A), it, view, sp, pivot_slot, _p(pl), ctypes.byref(e),
+                                      ctypes.byref(ch), _p(slots), _p(planes), _p(en), cap)
+        if n < 0:
+            raise ValueError("bad pivot or superpixel (%d)" % n)
+        return pl, e.value, ch.value, slots[:n], planes[:n], en[:n]
 
     def render_depth(self, planes, view):
         planes = np.ascontiguousarray(planes, np.float64)

@@ -628,7 +628,7 @@ static void consider_cell(const slfo_ctx *c, const double *A, int r, int s, int 
  * normals at the winner's centroid depth.  Slot numbers: 0 current, 1+j
  * ring, 9 + 8 (m/step - 1) + j far, 1000 + j normals. */
 static int refine_one(const slfo_ctx *c, const double *A, int iter, int r, int s, double plane[4], double *energy,
-                      int32_t *choice, double *margin, trace_t *tr)
+                      int32_t *choice, double *margin, trace_t *tr, int pivot_slot)
 {
     if (r < 0 || r >= c->V || s < 0 || s >= c->sp_off[r + 1] - c->sp_off[r] || iter < 1) return -1;
     int64_t g = gid(c, r, s);
@@ -659,6 +659,20 @@ static int refine_one(const slfo_ctx *c, const double *A, int iter, int r, int s
             int k = cell_at(c, r, s, m * RING_DX[j], m * RING_DY[j]);
             if (k >= 0) consider_cell(c, A, r, s, k, 9 + 8 * (m / step - 1) + j, &st);
         }
+
+    /* Test hook: resolve the propagation stage toward `pivot_slot` (one of the
+     * evaluated propagation slots), as a tie-break at a near-tie would. */
+    if (pivot_slot >= 0 && tr) {
+        int found = -1;
+        for (int k = 0; k < tr->n; ++k)
+            if (tr->slots[k] == pivot_slot) found = k;
+        if (found < 0) return -2;
+        st.best_slot = pivot_slot;
+        st.best_E = tr->energies[found];
+        memcpy(st.best_plane, tr->planes + 4 * found, sizeof st.best_plane);
+        st.second_E = -INFINITY;
+        st.evaluated = 1;
+    }
 
     /* triangle normals through the 3D centroids of s (at the winner's depth)
      * and of two adjacent ring neighbours (at their depths in A) */
@@ -708,7 +722,7 @@ static int refine_one(const slfo_ctx *c, const double *A, int iter, int r, int s
 int slfo_refine_sp(const slfo_ctx *c, const double *A, int iter, int r, int s, double plane[4], double *energy,
                    int32_t *choice, double *margin)
 {
-    return refine_one(c, A, iter, r, s, plane, energy, choice, margin, NULL);
+    return refine_one(c, A, iter, r, s, plane, energy, choice, margin, NULL, -1);
 }
 
 int slfo_refine_trace(const slfo_ctx *c, const double *A, int iter, int r, int s, int32_t *slots, double *planes,
@@ -717,7 +731,16 @@ int slfo_refine_trace(const slfo_ctx *c, const double *A, int iter, int r, int s
     trace_t tr = {slots, planes, energies, cap, 0};
     double pl[4], e, m;
     int32_t ch;
-    int rc = refine_one(c, A, iter, r, s, pl, &e, &ch, &m, &tr);
+    int rc = refine_one(c, A, iter, r, s, pl, &e, &ch, &m, &tr, -1);
+    return rc < 0 ? rc : tr.n;
+}
+
+int slfo_refine_pivot(const slfo_ctx *c, const double *A, int iter, int r, int s, int pivot_slot, double plane[4],
+                      double *energy, int32_t *choice, int32_t *slots, double *planes, double *energies, int cap)
+{
+    trace_t tr = {slots, planes, energies, cap, 0};
+    double m;
+    int rc = refine_one(c, A, iter, r, s, plane, energy, choice, &m, &tr, pivot_slot);
     return rc < 0 ? rc : tr.n;
 }
 
@@ -731,7 +754,7 @@ int slfo_refine_all(const slfo_ctx *c, const double *A, int iter, double *B, dou
         int v = 0;
         while (g >= c->sp_off[v + 1]) ++v;
         bad |= refine_one(c, A, iter, v, (int)(g - c->sp_off[v]), B + 4 * g, energy + g, choice + g, margin + g,
-                          NULL) != 0;
+                          NULL, -1) != 0;
     }
     return bad ? -1 : 0;
 }

@@ -96,6 +96,15 @@ int slfo_refine_all(const slfo_ctx *c, const double *A, int iter, double *B, dou
 int slfo_refine_trace(const slfo_ctx *c, const double *A, int iter, int view, int sp, int32_t *slots,
                       double *planes, double *energies, int cap);
 
+/* Test hook: the refinement step with its propagation stage resolved toward
+ * `pivot_slot` (an evaluated propagation slot), as a tie-break would: the
+ * normals pivot at that candidate and replace it only on strict improvement.
+ * Fills the final plane / energy / choice and the trace (propagation slots,
+ * then the normals); returns the trace length, -2 if the slot was not
+ * evaluated, or < 0 on bad arguments. */
+int slfo_refine_pivot(const slfo_ctx *c, const double *A, int iter, int view, int sp, int pivot_slot, double plane[4],
+                      double *energy, int32_t *choice, int32_t *slots, double *planes, double *energies, int cap);
+
 /* per-pixel depth of view `view` from planes [S][4]; 0 where undefined */
 int slfo_render_depth(const slfo_ctx *c, const double *planes, int view, double *out);
 

@@ -1,0 +1,812 @@
+// Host layer of libslf: the C ABI declared in include/slf.h.  Validates
+// arguments, owns device buffers, composes per-view-pair geometry in FP64 and
+// enqueues the kernels of slf_kernels.hip on the context's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "slf.h"
+#include "slf_internal.h"
+
+using namespace slf;
+
+namespace {
+
+struct ViewHost {
+  int W = 0, H = 0;
+  double K[9], R[9], t[3], Kinv[9];
+  int gw = 0, gh = 0;
+  bool has_img = false, has_lab = false, has_planes = false;
+  std::vector<int> nbrs;
+};
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+void inv3(const double *m, double *o) {
+  const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5], g = m[6], h = m[7], i = m[8];
+  const double c00 = e * i - f * h, c01 = f * g - d * i, c02 = d * h - e * g;
+  const double det = a * c00 + b * c01 + c * c02;
+  o[0] = c00 / det;
+  o[1] = (c * h - b * i) / det;
+  o[2] = (b * f - c * e) / det;
+  o[3] = c01 / det;
+  o[4] = (a * i - c * g) / det;
+  o[5] = (c * d - a * f) / det;
+  o[6] = c02 / det;
+  o[7] = (b * g - a * h) / det;
+  o[8] = (a * e - b * d) / det;
+}
+
+void mul3(const double *a, const double *b, double *o) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) o[3 * r + c] = a[3 * r] * b[c] + a[3 * r + 1] * b[3 + c] + a[3 * r + 2] * b[6 + c];
+}
+
+bool finite_all(const double *x, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+struct slf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  slf_params p;
+  std::string err;
+  std::vector<ViewHost> vh;
+  int V = 0;
+
+  // per-pixel device buffers
+  uint8_t *d_rgb = nullptr;
+  int *d_labels = nullptr;
+  void *d_quads = nullptr;
+  size_t quads_bytes = 0;
+  int quads_fmt = -1;
+  bool quads_dirty = true;
+  int64_t total_px = 0;
+
+  // geometry tables
+  std::vector<ViewDev> views_h;
+  std::vector<PairDev> pairs_h;
+  ViewDev *d_views = nullptr;
+  PairDev *d_pairs = nullptr;
+  bool geom_dirty = true;
+
+  // superpixel buffers
+  int S = 0, S_cap = 0;
+  bool sp_dirty = true;
+  int *d_count = nullptr, *d_sp_view = nullptr, *d_area = nullptr, *d_px_off = nullptr, *d_scan = nullptr;
+  int *d_err = nullptr;
+  int4 *d_bbox = nullptr;
+  float2 *d_centroid = nullptr;
+  double2 *d_centroid_d = nullptr;
+  float4 *d_colour = nullptr;
+  PixEntry *d_px = nullptr;
+  float4 *d_planes[2] = {nullptr, nullptr};
+  float4 *d_gtab[2] = {nullptr, nullptr};
+  float *d_energy = nullptr, *d_margin = nullptr;
+  int *d_choice = nullptr;
+  unsigned long long *d_work = nullptr;
+  float *d_depth_tmp = nullptr;
+  int64_t depth_tmp_n = 0;
+  int cur = 0;
+  std::vector<int> area_h;
+  std::vector<double2> cen_h;
+  uint64_t host_evals = 0, host_samples = 0;
+
+  int fail(int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+};
+
+int slf_ctx::fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  err = buf;
+  return code;
+}
+
+#define HIP_OR_FAIL(ctx, call)                                                                          \
+  do {                                                                                                  \
+    hipError_t e_ = (call);                                                                             \
+    if (e_ != hipSuccess)                                                                               \
+      return (ctx)->fail(e_ == hipErrorOutOfMemory ? SLF_ENOMEM : SLF_EDEVICE, "%s: %s", #call,         \
+                         hipGetErrorString(e_));                                                        \
+  } while (0)
+
+namespace {
+
+int params_check(slf_ctx *c, const slf_params *p) {
+  if (!p) return c->fail(SLF_EINVAL, "params is NULL");
+  if (p->struct_size != sizeof(slf_params))
+    return c->fail(SLF_EINVAL, "struct_size %u != %zu", p->struct_size, sizeof(slf_params));
+  if (p->levels < 1 || p->levels > (1 << 20)) return c->fail(SLF_EINVAL, "levels %d out of [1, 2^20]", p->levels);
+  if (!(p->d_min > 0) || !(p->d_max > p->d_min) || !std::isfinite(p->d_max))
+    return c->fail(SLF_EINVAL, "need 0 < d_min < d_max < inf");
+  if (!(p->tssd_T > 0) || !std::isfinite(p->tssd_T)) return c->fail(SLF_EINVAL, "tssd_T must be > 0");
+  if (!(p->sigma > 0) || !std::isfinite(p->sigma)) return c->fail(SLF_EINVAL, "sigma must be > 0");
+  if (!(p->alpha > 0) || !std::isfinite(p->alpha)) return c->fail(SLF_EINVAL, "alpha must be > 0");
+  if (!(p->eta >= 0) || !std::isfinite(p->eta)) return c->fail(SLF_EINVAL, "eta must be >= 0");
+  if (!(p->occ_tol >= 0) || !std::isfinite(p->occ_tol)) return c->fail(SLF_EINVAL, "occ_tol must be >= 0");
+  if (p->kernel_step < 1) return c->fail(SLF_EINVAL, "kernel_step must be >= 1");
+  if (p->term_mask > 7u) return c->fail(SLF_EINVAL, "term_mask must be in [0, 7]");
+  if (p->image_precision < 0 || p->image_precision > 2) return c->fail(SLF_EINVAL, "bad image_precision");
+  if (p->energy_mode < 0 || p->energy_mode > 1) return c->fail(SLF_EINVAL, "bad energy_mode");
+  if (p->homography_fp64 != 1) return c->fail(SLF_EUNSUPPORTED, "homography_fp64 must be 1");
+  return SLF_OK;
+}
+
+int ensure_alloc(slf_ctx *c, size_t bytes, void **ptr) {
+  hipError_t e = hipMalloc(ptr, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return c->fail(SLF_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  return SLF_OK;
+}
+
+void free_sp(slf_ctx *c) {
+  dfree(c->d_count);
+  dfree(c->d_sp_view);
+  dfree(c->d_area);
+  dfree(c->d_px_off);
+  dfree(c->d_scan);
+  dfree(c->d_bbox);
+  dfree(c->d_centroid);
+  dfree(c->d_centroid_d);
+  dfree(c->d_colour);
+  dfree(c->d_px);
+  for (int j = 0; j < 2; ++j) {
+    dfree(c->d_planes[j]);
+    dfree(c->d_gtab[j]);
+  }
+  dfree(c->d_energy);
+  dfree(c->d_margin);
+  dfree(c->d_choice);
+  c->S_cap = 0;
+}
+
+void free_all(slf_ctx *c) {
+  free_sp(c);
+  dfree(c->d_rgb);
+  dfree(c->d_labels);
+  if (c->d_quads) (void)hipFree(c->d_quads);
+  c->d_quads = nullptr;
+  c->quads_bytes = 0;
+  dfree(c->d_views);
+  dfree(c->d_pairs);
+  dfree(c->d_err);
+  dfree(c->d_work);
+  dfree(c->d_depth_tmp);
+}
+
+bool views_ready(const slf_ctx *c) {
+  if (c->V < 2) return false;
+  for (const auto &v : c->vh)
+    if (!v.has_img || !v.has_lab) return false;
+  return true;
+}
+
+// Per-view and per-pair geometry, composed in FP64 and rounded once.
+int build_geometry(slf_ctx *c) {
+  const int V = c->V;
+  c->views_h.assign(V, ViewDev{});
+  c->pairs_h.clear();
+  int sp = 0;
+  int64_t px = 0, qd = 0;
+  for (int v = 0; v < V; ++v) {
+    const ViewHost &h = c->vh[v];
+    ViewDev &d = c->views_h[v];
+    d.W = h.W;
+    d.H = h.H;
+    d.gw = h.gw;
+    d.gh = h.gh;
+    d.sp_off = sp;
+    d.pix_off = px;
+    d.quad_off = qd;
+    d.pair_off = (int)c->pairs_h.size();
+    d.n_pairs = (int)h.nbrs.size();
+    if (c->p.kernel_radius_init > 0) {
+      d.kr_init = c->p.kernel_radius_init;
+    } else {
+      const double S = std::sqrt((double)h.W * h.H / ((double)h.gw * h.gh));
+      d.kr_init = (int)std::floor(std::min(h.W, h.H) / (2.0 * S));
+    }
+    for (int j = 0; j < 9; ++j) {
+      d.Kinv[j] = (float)h.Kinv[j];
+      d.Kinv_d[j] = h.Kinv[j];
+    }
+    const int64_t K = (int64_t)h.gw * h.gh;
+    if ((int64_t)sp + K > (int64_t)1 << 30) return c->fail(SLF_EUNSUPPORTED, "too many superpixels");
+    sp += (int)K;
+    px += (int64_t)h.W * h.H;
+    qd += (int64_t)(h.W - 1) * (h.H - 1);
+    // pairs: A = K_i R_ri K_r^-1, b = K_i t_ri, R_ri = R_i R_r^T, t_ri = t_i - R_ri t_r
+    for (int i : h.nbrs) {
+      const ViewHost &hi = c->vh[i];
+      double RrT[9], Rri[9], tri[3], T1[9], A[9];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) RrT[3 * a + b] = h.R[3 * b + a];
+      mul3(hi.R, RrT, Rri);
+      for (int a = 0; a < 3; ++a)
+        tri[a] = hi.t[a] - (Rri[3 * a] * h.t[0] + Rri[3 * a + 1] * h.t[1] + Rri[3 * a + 2] * h.t[2]);
+      mul3(hi.K, Rri, T1);
+      mul3(T1, h.Kinv, A);
+      PairDev pd{};
+      for (int j = 0; j < 9; ++j) {
+        pd.A[j] = (float)A[j];
+        pd.A_d[j] = A[j];
+      }
+      for (int a = 0; a < 3; ++a) {
+        const double bb = hi.K[3 * a] * tri[0] + hi.K[3 * a + 1] * tri[1] + hi.K[3 * a + 2] * tri[2];
+        pd.b[a] = (float)bb;
+        pd.b_d[a] = bb;
+      }
+      pd.i = i;
+      c->pairs_h.push_back(pd);
+    }
+  }
+  c->S = sp;
+  c->total_px = px;
+  dfree(c->d_views);
+  dfree(c->d_pairs);
+  int rc;
+  if ((rc = ensure_alloc(c, sizeof(ViewDev) * V, (void **)&c->d_views))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(PairDev) * std::max<size_t>(1, c->pairs_h.size()), (void **)&c->d_pairs)))
+    return rc;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_views, c->views_h.data(), sizeof(ViewDev) * V, hipMemcpyHostToDevice,
+                                c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_pairs, c->pairs_h.data(), sizeof(PairDev) * c->pairs_h.size(),
+                                hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->geom_dirty = false;
+  return SLF_OK;
+}
+
+int alloc_sp(slf_ctx *c) {
+  if (c->S <= c->S_cap && c->d_px) return SLF_OK;
+  free_sp(c);
+  const size_t S = (size_t)c->S;
+  const size_t nb = (S + 4095) / 4096 + 1;
+  int rc;
+  if ((rc = ensure_alloc(c, sizeof(int) * S, (void **)&c->d_count))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(int) * S, (void **)&c->d_sp_view))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(int) * S, (void **)&c->d_area))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(int) * (S + 1), (void **)&c->d_px_off))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(int) * nb, (void **)&c->d_scan))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(int4) * S, (void **)&c->d_bbox))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(float2) * S, (void **)&c->d_centroid))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(double2) * S, (void **)&c->d_centroid_d))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(float4) * S, (void **)&c->d_colour))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(PixEntry) * (size_t)c->total_px, (void **)&c->d_px))) return rc;
+  for (int j = 0; j < 2; ++j) {
+    if ((rc = ensure_alloc(c, sizeof(float4) * S, (void **)&c->d_planes[j]))) return rc;
+    if ((rc = ensure_alloc(c, sizeof(float4) * S, (void **)&c->d_gtab[j]))) return rc;
+  }
+  if ((rc = ensure_alloc(c, sizeof(float) * S, (void **)&c->d_energy))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(float) * S, (void **)&c->d_margin))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(int) * S, (void **)&c->d_choice))) return rc;
+  c->S_cap = c->S;
+  return SLF_OK;
+}
+
+// Geometry tables, image texels and superpixel lists, rebuilt when inputs changed.
+int ensure_setup(slf_ctx *c) {
+  if (!views_ready(c)) return c->fail(SLF_ESTATE, "cameras, images and labels must be set for every view");
+  int rc;
+  if (c->geom_dirty) {
+    const int old_S = c->S;
+    if ((rc = build_geometry(c))) return rc;
+    if (c->S != old_S) c->sp_dirty = true;
+  }
+  const int fmt = c->p.image_precision;
+  if (c->quads_dirty || c->quads_fmt != fmt) {
+    int64_t texels = 0;
+    for (const auto &v : c->vh) texels += (int64_t)(v.W - 1) * (v.H - 1);
+    const size_t need = (size_t)texels * quad_bytes(fmt);
+    if (need > c->quads_bytes) {
+      if (c->d_quads) (void)hipFree(c->d_quads);
+      c->d_quads = nullptr;
+      c->quads_bytes = 0;
+      if ((rc = ensure_alloc(c, need, &c->d_quads))) return rc;
+      c->quads_bytes = need;
+    }
+    for (int v = 0; v < c->V; ++v) {
+      const ViewDev &d = c->views_h[v];
+      HIP_OR_FAIL(c, launch_quads(fmt, c->d_rgb + 3 * d.pix_off, 3 * (int64_t)d.W, d.W, d.H, c->d_quads, d.quad_off,
+                                  c->stream));
+    }
+    c->quads_fmt = fmt;
+    c->quads_dirty = false;
+  }
+  if (c->sp_dirty) {
+    if ((rc = alloc_sp(c))) return rc;
+    HIP_OR_FAIL(c, launch_sp_build(c->d_views, c->views_h.data(), c->V, c->d_labels, c->d_rgb, c->S, c->d_count,
+                                   c->d_bbox, c->d_px_off, c->d_scan, c->d_px, c->d_area, c->d_centroid,
+                                   c->d_centroid_d, c->d_colour, c->d_sp_view, c->d_err, c->stream));
+    int herr = 0;
+    HIP_OR_FAIL(c, hipMemcpyAsync(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->area_h.resize(c->S);
+    c->cen_h.resize(c->S);
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->area_h.data(), c->d_area, sizeof(int) * c->S, hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->cen_h.data(), c->d_centroid_d, sizeof(double2) * c->S, hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (herr & 1) return c->fail(SLF_EINVAL, "a label is outside [0, grid_w * grid_h)");
+    if (herr) return c->fail(SLF_EDEVICE, "superpixel list build inconsistent (flag %d)", herr);
+    for (auto &v : c->vh) v.has_planes = false;
+    c->sp_dirty = false;
+  }
+  return SLF_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+void slf_default_params(slf_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->struct_size = sizeof(slf_params);
+  p->levels = 64;
+  p->d_min = 2.0;
+  p->d_max = 8.0;
+  p->seed = 0x5EED;
+  p->jitter = 1;
+  p->tssd_T = 0.04f;
+  p->sigma = 0.05f;
+  p->alpha = 0.1f;
+  p->eta = 0.5f;
+  p->occ_tol = 1e-3f;
+  p->kernel_step = 5;
+  p->kernel_radius_init = 0;
+  p->term_mask = 7u;
+  p->image_precision = SLF_IMAGE_U8;
+  p->homography_fp64 = 1;
+  p->energy_mode = 0;
+}
+
+const char *slf_status_string(int s) {
+  switch (s) {
+    case SLF_OK: return "SLF_OK";
+    case SLF_EINVAL: return "SLF_EINVAL: invalid argument";
+    case SLF_ESTATE: return "SLF_ESTATE: call out of order";
+    case SLF_ENOMEM: return "SLF_ENOMEM: out of memory";
+    case SLF_EDEVICE: return "SLF_EDEVICE: HIP runtime error";
+    case SLF_EUNSUPPORTED: return "SLF_EUNSUPPORTED: not supported";
+    default: return "unknown status";
+  }
+}
+
+const char *slf_last_error(const slf_ctx *ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+int slf_create(int device_ordinal, slf_ctx **out) {
+  if (!out) return SLF_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return SLF_EDEVICE;
+  if (device_ordinal < 0 || device_ordinal >= n) return SLF_EINVAL;
+  slf_ctx *c = new (std::nothrow) slf_ctx();
+  if (!c) return SLF_ENOMEM;
+  c->device = device_ordinal;
+  slf_default_params(&c->p);
+  if (hipSetDevice(device_ordinal) != hipSuccess) {
+    delete c;
+    return SLF_EDEVICE;
+  }
+  if (hipMalloc((void **)&c->d_err, sizeof(int)) != hipSuccess ||
+      hipMalloc((void **)&c->d_work, 2 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_work, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+    free_all(c);
+    delete c;
+    return SLF_ENOMEM;
+  }
+  *out = c;
+  return SLF_OK;
+}
+
+int slf_destroy(slf_ctx *c) {
+  if (!c) return SLF_EINVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+  return SLF_OK;
+}
+
+int slf_set_stream(slf_ctx *c, void *stream) {
+  if (!c) return SLF_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return SLF_OK;
+}
+
+int slf_set_params(slf_ctx *c, const slf_params *p) {
+  if (!c) return SLF_EINVAL;
+  int rc = params_check(c, p);
+  if (rc) return rc;
+  const bool radius_changed = p->kernel_radius_init != c->p.kernel_radius_init;
+  c->p = *p;
+  if (radius_changed) c->geom_dirty = true;
+  return SLF_OK;
+}
+
+int slf_set_cameras(slf_ctx *c, int n_views, const int32_t *wh, const double *K, const double *R, const double *t) {
+  if (!c) return SLF_EINVAL;
+  if (n_views < 2 || n_views > 4096) return c->fail(SLF_EINVAL, "n_views %d out of [2, 4096]", n_views);
+  if (!wh || !K || !R || !t) return c->fail(SLF_EINVAL, "NULL camera array");
+  std::vector<ViewHost> vh(n_views);
+  int64_t total = 0;
+  for (int v = 0; v < n_views; ++v) {
+    ViewHost &h = vh[v];
+    h.W = wh[2 * v];
+    h.H = wh[2 * v + 1];
+    if (h.W < 2 || h.H < 2) return c->fail(SLF_EINVAL, "view %d: W, H must be >= 2", v);
+    if (h.W > 65535 || h.H > 65535) return c->fail(SLF_EUNSUPPORTED, "view %d: W, H must be <= 65535", v);
+    std::memcpy(h.K, K + 9 * v, sizeof h.K);
+    std::memcpy(h.R, R + 9 * v, sizeof h.R);
+    std::memcpy(h.t, t + 3 * v, sizeof h.t);
+    if (!finite_all(h.K, 9) || !finite_all(h.R, 9) || !finite_all(h.t, 3))
+      return c->fail(SLF_EINVAL, "view %d: non-finite camera", v);
+    if (h.K[6] != 0.0 || h.K[7] != 0.0 || h.K[8] != 1.0) return c->fail(SLF_EINVAL, "view %d: K's last row must be (0,0,1)", v);
+    const double det = h.K[0] * (h.K[4] * h.K[8] - h.K[5] * h.K[7]) - h.K[1] * (h.K[3] * h.K[8] - h.K[5] * h.K[6]) +
+                       h.K[2] * (h.K[3] * h.K[7] - h.K[4] * h.K[6]);
+    if (!(std::fabs(det) > 0.0)) return c->fail(SLF_EINVAL, "view %d: K is singular", v);
+    double RRt[9], Rt[9];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) Rt[3 * a + b] = h.R[3 * b + a];
+    mul3(h.R, Rt, RRt);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        if (std::fabs(RRt[3 * a + b] - (a == b ? 1.0 : 0.0)) > 1e-6)
+          return c->fail(SLF_EINVAL, "view %d: R is not orthonormal", v);
+    const double detR = h.R[0] * (h.R[4] * h.R[8] - h.R[5] * h.R[7]) - h.R[1] * (h.R[3] * h.R[8] - h.R[5] * h.R[6]) +
+                        h.R[2] * (h.R[3] * h.R[7] - h.R[4] * h.R[6]);
+    if (!(detR > 0.0)) return c->fail(SLF_EINVAL, "view %d: R is not a rotation", v);
+    inv3(h.K, h.Kinv);
+    total += (int64_t)h.W * h.H;
+    for (int i = 0; i < n_views; ++i)
+      if (i != v) h.nbrs.push_back(i);
+  }
+  if (total >= ((int64_t)1 << 31)) return c->fail(SLF_EUNSUPPORTED, "more than 2^31 pixels in total");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  free_sp(c);
+  dfree(c->d_rgb);
+  dfree(c->d_labels);
+  if (c->d_quads) (void)hipFree(c->d_quads);
+  c->d_quads = nullptr;
+  c->quads_bytes = 0;
+  c->vh = vh;
+  c->V = n_views;
+  c->total_px = total;
+  int rc;
+  if ((rc = ensure_alloc(c, (size_t)total * 3, (void **)&c->d_rgb))) return rc;
+  if ((rc = ensure_alloc(c, (size_t)total * sizeof(int), (void **)&c->d_labels))) return rc;
+  c->geom_dirty = true;
+  c->sp_dirty = true;
+  c->quads_dirty = true;
+  c->S = 0;
+  return SLF_OK;
+}
+
+int slf_set_neighbors(slf_ctx *c, int view, int n, const int32_t *views) {
+  if (!c) return SLF_EINVAL;
+  if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
+  if (n < 1 || n > c->V - 1 || !views) return c->fail(SLF_EINVAL, "need 1 <= n <= n_views - 1 neighbour views");
+  std::vector<int> nb(views, views + n);
+  for (int j = 0; j < n; ++j) {
+    if (nb[j] < 0 || nb[j] >= c->V || nb[j] == view) return c->fail(SLF_EINVAL, "bad neighbour view %d", nb[j]);
+    for (int k = 0; k < j; ++k)
+      if (nb[k] == nb[j]) return c->fail(SLF_EINVAL, "neighbour view %d repeated", nb[j]);
+  }
+  c->vh[view].nbrs = nb;
+  c->geom_dirty = true;
+  return SLF_OK;
+}
+
+static int64_t pix_off_of(const slf_ctx *c, int view) {
+  int64_t o = 0;
+  for (int v = 0; v < view; ++v) o += (int64_t)c->vh[v].W * c->vh[v].H;
+  return o;
+}
+
+int slf_set_image_rgb8(slf_ctx *c, int view, const uint8_t *rgb, int64_t stride, int is_device) {
+  if (!c) return SLF_EINVAL;
+  if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
+  const ViewHost &h = c->vh[view];
+  if (!rgb) return c->fail(SLF_EINVAL, "rgb is NULL");
+  if (stride < 3 * (int64_t)h.W) return c->fail(SLF_EINVAL, "row stride %lld < 3 W", (long long)stride);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  uint8_t *dst = c->d_rgb + 3 * pix_off_of(c, view);
+  HIP_OR_FAIL(c, hipMemcpy2DAsync(dst, 3 * (size_t)h.W, rgb, (size_t)stride, 3 * (size_t)h.W, (size_t)h.H,
+                                  is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  if (!is_device) HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->vh[view].has_img = true;
+  c->quads_dirty = true;
+  c->sp_dirty = true;  // pixel entries carry the reference colours
+  return SLF_OK;
+}
+
+int slf_set_labels(slf_ctx *c, int view, const int32_t *labels, int64_t stride, int gw, int gh, int is_device) {
+  if (!c) return SLF_EINVAL;
+  if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
+  const ViewHost &h = c->vh[view];
+  if (!labels) return c->fail(SLF_EINVAL, "labels is NULL");
+  if (stride < h.W) return c->fail(SLF_EINVAL, "row stride %lld < W", (long long)stride);
+  if (gw < 1 || gh < 1 || (int64_t)gw * gh > (1 << 24)) return c->fail(SLF_EINVAL, "grid %d x %d invalid", gw, gh);
+  if (!is_device) {
+    const int K = gw * gh;
+    for (int y = 0; y < h.H; ++y)
+      for (int x = 0; x < h.W; ++x) {
+        const int l = labels[(int64_t)y * stride + x];
+        if (l < 0 || l >= K) return c->fail(SLF_EINVAL, "label %d at (%d, %d) outside [0, %d)", l, x, y, K);
+      }
+  }
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  int *dst = c->d_labels + pix_off_of(c, view);
+  HIP_OR_FAIL(c, hipMemcpy2DAsync(dst, sizeof(int) * (size_t)h.W, labels, sizeof(int) * (size_t)stride,
+                                  sizeof(int) * (size_t)h.W, (size_t)h.H,
+                                  is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+  if (!is_device) HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  ViewHost &hv = c->vh[view];
+  if (hv.gw != gw || hv.gh != gh) c->geom_dirty = true;
+  hv.gw = gw;
+  hv.gh = gh;
+  hv.has_lab = true;
+  c->sp_dirty = true;
+  return SLF_OK;
+}
+
+int slf_prepare(slf_ctx *c) {
+  if (!c) return SLF_EINVAL;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  return ensure_setup(c);
+}
+
+int slf_sweep(slf_ctx *c) {
+  if (!c) return SLF_EINVAL;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  int rc = ensure_setup(c);
+  if (rc) return rc;
+  SweepArgs a{};
+  a.views = c->d_views;
+  a.pairs = c->d_pairs;
+  a.sp_view = c->d_sp_view;
+  a.area = c->d_area;
+  a.px_off = c->d_px_off;
+  a.px = c->d_px;
+  a.quads = c->d_quads;
+  a.S = c->S;
+  a.levels = c->p.levels;
+  a.qmin = 1.0 / c->p.d_max;
+  a.dq = (1.0 / c->p.d_min - 1.0 / c->p.d_max) / c->p.levels;
+  a.seed = c->p.seed;
+  a.jitter = c->p.jitter;
+  a.T255 = c->p.tssd_T * 255.f * 255.f;
+  a.planes = c->d_planes[c->cur];
+  a.gtab = c->d_gtab[c->cur];
+  a.cost = c->d_energy;
+  a.choice = c->d_choice;
+  a.margin = c->d_margin;
+  HIP_OR_FAIL(c, launch_sweep(c->p.image_precision, a, c->stream));
+  for (int v = 0; v < c->V; ++v) {
+    const ViewDev &d = c->views_h[v];
+    uint64_t nonempty = 0, px = 0;
+    for (int s = 0; s < d.gw * d.gh; ++s) {
+      const int A = c->area_h[d.sp_off + s];
+      nonempty += A > 0;
+      px += (uint64_t)A;
+    }
+    c->host_evals += nonempty * (uint64_t)c->p.levels;
+    c->host_samples += px * (uint64_t)d.n_pairs * (uint64_t)c->p.levels;
+    c->vh[v].has_planes = true;
+  }
+  return SLF_OK;
+}
+
+int slf_set_planes(slf_ctx *c, int view, const float *planes) {
+  if (!c) return SLF_EINVAL;
+  if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
+  if (!planes) return c->fail(SLF_EINVAL, "planes is NULL");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  int rc = ensure_setup(c);
+  if (rc) return rc;
+  const ViewDev &d = c->views_h[view];
+  const ViewHost &h = c->vh[view];
+  const int K = d.gw * d.gh;
+  std::vector<float4> pl(K), gt(K);
+  for (int s = 0; s < K; ++s) {
+    const int g = d.sp_off + s;
+    if (c->area_h[g] == 0) {
+      pl[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+      gt[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+      continue;
+    }
+    const double dd = planes[4 * s], n0 = planes[4 * s + 1], n1 = planes[4 * s + 2], n2 = planes[4 * s + 3];
+    if (!std::isfinite(dd) || !(dd > 0) || !std::isfinite(n0) || !std::isfinite(n1) || !std::isfinite(n2))
+      return c->fail(SLF_EINVAL, "view %d cell %d: plane not finite or d <= 0", view, s);
+    if (std::fabs(std::sqrt(n0 * n0 + n1 * n1 + n2 * n2) - 1.0) > 1e-3)
+      return c->fail(SLF_EINVAL, "view %d cell %d: normal is not unit length", view, s);
+    const double cu = c->cen_h[g].x, cv = c->cen_h[g].y;
+    const double rx = h.Kinv[0] * cu + h.Kinv[1] * cv + h.Kinv[2];
+    const double ry = h.Kinv[3] * cu + h.Kinv[4] * cv + h.Kinv[5];
+    const double rz = h.Kinv[6] * cu + h.Kinv[7] * cv + h.Kinv[8];
+    const double tt = n0 * rx + n1 * ry + n2 * rz;
+    if (!(tt > 0)) return c->fail(SLF_EINVAL, "view %d cell %d: plane does not face the camera", view, s);
+    const double delta = dd * tt;
+    pl[s] = make_float4((float)dd, (float)n0, (float)n1, (float)n2);
+    gt[s] = make_float4((float)((n0 * h.Kinv[0] + n1 * h.Kinv[3] + n2 * h.Kinv[6]) / delta),
+                        (float)((n0 * h.Kinv[1] + n1 * h.Kinv[4] + n2 * h.Kinv[7]) / delta),
+                        (float)((n0 * h.Kinv[2] + n1 * h.Kinv[5] + n2 * h.Kinv[8]) / delta), 0.f);
+  }
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_planes[c->cur] + d.sp_off, pl.data(), sizeof(float4) * K, hipMemcpyHostToDevice,
+                                c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_gtab[c->cur] + d.sp_off, gt.data(), sizeof(float4) * K, hipMemcpyHostToDevice,
+                                c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->vh[view].has_planes = true;
+  return SLF_OK;
+}
+
+int slf_propagate(slf_ctx *c, int first_iter, int n_iters) {
+  if (!c) return SLF_EINVAL;
+  if (first_iter < 1 || n_iters < 0) return c->fail(SLF_EINVAL, "need first_iter >= 1 and n_iters >= 0");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  int rc = ensure_setup(c);
+  if (rc) return rc;
+  for (const auto &v : c->vh)
+    if (!v.has_planes) return c->fail(SLF_ESTATE, "every view needs planes (slf_sweep or slf_set_planes)");
+  RefineArgs a{};
+  a.views = c->d_views;
+  a.pairs = c->d_pairs;
+  a.sp_view = c->d_sp_view;
+  a.area = c->d_area;
+  a.px_off = c->d_px_off;
+  a.px = c->d_px;
+  a.centroid_d = c->d_centroid_d;
+  a.colour = c->d_colour;
+  a.labels = c->d_labels;
+  a.quads = c->d_quads;
+  a.energy = c->d_energy;
+  a.choice = c->d_choice;
+  a.margin = c->d_margin;
+  a.work = c->d_work;
+  a.S = c->S;
+  a.kernel_step = c->p.kernel_step;
+  a.energy_mode = c->p.energy_mode;
+  a.term_mask = c->p.term_mask;
+  a.inv2sig2 = 1.f / (2.f * c->p.sigma * c->p.sigma);
+  a.inv2alpha2 = 1.f / (2.f * c->p.alpha * c->p.alpha);
+  a.eta = c->p.eta;
+  a.occ_tol = c->p.occ_tol;
+  a.T255 = c->p.tssd_T * 255.f * 255.f;
+  for (int it = first_iter; it < first_iter + n_iters; ++it) {
+    a.iter = it;
+    a.planesA = c->d_planes[c->cur];
+    a.gtabA = c->d_gtab[c->cur];
+    a.planesB = c->d_planes[1 - c->cur];
+    a.gtabB = c->d_gtab[1 - c->cur];
+    HIP_OR_FAIL(c, launch_refine(c->p.image_precision, a, c->stream));
+    c->cur = 1 - c->cur;
+  }
+  return SLF_OK;
+}
+
+int slf_get_planes(slf_ctx *c, int view, float *planes, float *energy, int32_t *choice, float *margin) {
+  if (!c) return SLF_EINVAL;
+  if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
+  if (c->sp_dirty || c->views_h.empty() || !c->vh[view].has_planes)
+    return c->fail(SLF_ESTATE, "no planes for view %d", view);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  const ViewDev &d = c->views_h[view];
+  const size_t K = (size_t)d.gw * d.gh;
+  if (planes)
+    HIP_OR_FAIL(c, hipMemcpyAsync(planes, c->d_planes[c->cur] + d.sp_off, sizeof(float4) * K, hipMemcpyDeviceToHost,
+                                  c->stream));
+  if (energy)
+    HIP_OR_FAIL(c, hipMemcpyAsync(energy, c->d_energy + d.sp_off, sizeof(float) * K, hipMemcpyDeviceToHost, c->stream));
+  if (choice)
+    HIP_OR_FAIL(c, hipMemcpyAsync(choice, c->d_choice + d.sp_off, sizeof(int) * K, hipMemcpyDeviceToHost, c->stream));
+  if (margin)
+    HIP_OR_FAIL(c, hipMemcpyAsync(margin, c->d_margin + d.sp_off, sizeof(float) * K, hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return SLF_OK;
+}
+
+int slf_get_depth(slf_ctx *c, int view, float *out, int64_t stride, int is_device) {
+  if (!c) return SLF_EINVAL;
+  if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
+  if (!out) return c->fail(SLF_EINVAL, "out is NULL");
+  if (c->sp_dirty || c->views_h.empty() || !c->vh[view].has_planes)
+    return c->fail(SLF_ESTATE, "no planes for view %d", view);
+  const ViewDev &d = c->views_h[view];
+  if (stride < d.W) return c->fail(SLF_EINVAL, "row stride %lld < W", (long long)stride);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  if (is_device) {
+    HIP_OR_FAIL(c, launch_depth(c->d_views, d, view, c->d_labels, c->d_gtab[c->cur], out, stride, c->stream));
+    return SLF_OK;
+  }
+  const int64_t n = (int64_t)d.W * d.H;
+  if (n > c->depth_tmp_n) {
+    dfree(c->d_depth_tmp);
+    int rc = ensure_alloc(c, sizeof(float) * n, (void **)&c->d_depth_tmp);
+    if (rc) return rc;
+    c->depth_tmp_n = n;
+  }
+  HIP_OR_FAIL(c, launch_depth(c->d_views, d, view, c->d_labels, c->d_gtab[c->cur], c->d_depth_tmp, d.W, c->stream));
+  HIP_OR_FAIL(c, hipMemcpy2DAsync(out, sizeof(float) * stride, c->d_depth_tmp, sizeof(float) * d.W,
+                                  sizeof(float) * d.W, d.H, hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return SLF_OK;
+}
+
+int slf_get_superpixels(slf_ctx *c, int view, int32_t *area, float *centroid, float *colour) {
+  if (!c) return SLF_EINVAL;
+  if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
+  if (c->sp_dirty || c->views_h.empty()) return c->fail(SLF_ESTATE, "superpixels not built yet");
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  const ViewDev &d = c->views_h[view];
+  const size_t K = (size_t)d.gw * d.gh;
+  if (area) std::memcpy(area, c->area_h.data() + d.sp_off, sizeof(int) * K);
+  if (centroid)
+    for (size_t s = 0; s < K; ++s) {
+      centroid[2 * s] = (float)c->cen_h[d.sp_off + s].x;
+      centroid[2 * s + 1] = (float)c->cen_h[d.sp_off + s].y;
+    }
+  if (colour) {
+    std::vector<float4> tmp(K);
+    HIP_OR_FAIL(c, hipMemcpyAsync(tmp.data(), c->d_colour + d.sp_off, sizeof(float4) * K, hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    for (size_t s = 0; s < K; ++s) {
+      colour[3 * s] = tmp[s].x;
+      colour[3 * s + 1] = tmp[s].y;
+      colour[3 * s + 2] = tmp[s].z;
+    }
+  }
+  return SLF_OK;
+}
+
+int slf_get_work(slf_ctx *c, uint64_t *evals, uint64_t *samples) {
+  if (!c) return SLF_EINVAL;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  unsigned long long w[2] = {0, 0};
+  HIP_OR_FAIL(c, hipMemcpyAsync(w, c->d_work, sizeof w, hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (evals) *evals = c->host_evals + w[0];
+  if (samples) *samples = c->host_samples + w[1];
+  return SLF_OK;
+}
+
+int slf_reset_work(slf_ctx *c) {
+  if (!c) return SLF_EINVAL;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipMemsetAsync(c->d_work, 0, 2 * sizeof(unsigned long long), c->stream));
+  c->host_evals = c->host_samples = 0;
+  return SLF_OK;
+}
+
+int slf_synchronize(slf_ctx *c) {
+  if (!c) return SLF_EINVAL;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return SLF_OK;
+}
+
+}  // extern "C"

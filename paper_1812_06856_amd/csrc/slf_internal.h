@@ -1,0 +1,109 @@
+// Internal device-side layout shared by the kernels and the host layer of libslf.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "slf.h"
+
+namespace slf {
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+constexpr int kMaxNeighbors = 64;
+
+// Device image storage formats (texel = the four bilinear taps of a pixel).
+enum { SLF_FMT_U8 = SLF_IMAGE_U8, SLF_FMT_F16 = SLF_IMAGE_F16, SLF_FMT_F32 = SLF_IMAGE_F32 };
+
+// Per-view geometry and buffer offsets, in device memory.
+struct ViewDev {
+  int W, H, gw, gh;
+  int sp_off;          // first global superpixel index of this view
+  int pair_off;        // first entry of this view's neighbour list in the pair table
+  int n_pairs;         // |N(r)|
+  int kr_init;         // initial propagation kernel radius, grid cells
+  int64_t pix_off;     // first pixel of this view in per-pixel arrays (labels, rgb)
+  int64_t quad_off;    // first texel of this view in the quad image ((W-1) x (H-1) texels)
+  float Kinv[9];       // K^-1 rounded to FP32
+  float pad1[3];
+  double Kinv_d[9];    // K^-1 in FP64
+  double pad2;
+};
+
+// Geometry of one (reference r, neighbour i) pair: for a plane with
+// inverse-depth row g (1/D(p) = g . p~) in camera r, the plane-induced
+// homography is H = A + b g^T with A = K_i R_ri K_r^-1 and b = K_i t_ri.
+struct PairDev {
+  float A[9];
+  float b[3];
+  int i;               // neighbour view
+  int pad[3];
+  double A_d[9];
+  double b_d[3];
+};
+
+// Packed pixel-list entry: x = u | v << 16, y = RGBA8 of the pixel.
+using PixEntry = uint2;
+
+struct SweepArgs {
+  const ViewDev *views;
+  const PairDev *pairs;
+  const int *sp_view;
+  const int *area;
+  const int *px_off;
+  const PixEntry *px;
+  const void *quads;
+  int S;
+  int levels;
+  double qmin, dq;     // inverse-depth range start and bin width
+  uint64_t seed;
+  int jitter;
+  float T255;          // truncation in squared 0..255 units
+  float4 *planes;      // out
+  float4 *gtab;        // out: inverse-depth row (g0, g1, g2, 0) per superpixel
+  float *cost;         // out
+  int *choice;         // out
+  float *margin;       // out
+};
+
+struct RefineArgs {
+  const ViewDev *views;
+  const PairDev *pairs;
+  const int *sp_view;
+  const int *area;
+  const int *px_off;
+  const PixEntry *px;
+  const double2 *centroid_d;  // centroids in FP64
+  const float4 *colour;   // mean colour in [0,1]
+  const int *labels;      // all views
+  const void *quads;      // images (data-only energy mode)
+  const float4 *planesA;  // state read
+  const float4 *gtabA;
+  float4 *planesB;        // state written
+  float4 *gtabB;
+  float *energy;
+  int *choice;
+  float *margin;
+  unsigned long long *work;  // [0] evals, [1] samples
+  int S;
+  int iter;
+  int kernel_step;
+  int energy_mode;
+  unsigned term_mask;
+  float inv2sig2, inv2alpha2, eta, occ_tol, T255;
+};
+
+// Host-side launchers (slf_kernels.hip).
+hipError_t launch_quads(int fmt, const uint8_t *rgb, int64_t rgb_stride, int W, int H, void *quads,
+                        int64_t quad_off, hipStream_t st);
+hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V, const int *labels,
+                           const uint8_t *rgb, int S, int *count, int4 *bbox, int *px_off, int *scan_tmp,
+                           PixEntry *px, int *area, float2 *centroid, double2 *centroid_d, float4 *colour,
+                           int *sp_view, int *err, hipStream_t st);
+hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st);
+hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st);
+hipError_t launch_depth(const ViewDev *views_d, const ViewDev &vh, int view, const int *labels,
+                        const float4 *gtab, float *out, int64_t stride, hipStream_t st);
+size_t quad_bytes(int fmt);
+
+}  // namespace slf

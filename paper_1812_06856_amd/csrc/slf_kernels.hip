@@ -1,0 +1,899 @@
+// HIP kernels for gfx950: superpixel setup, plane sweep (TSSD), refinement
+// energy, depth readout.  One wavefront (64 lanes) owns one superpixel in the
+// sweep and refinement; lanes stride over the superpixel's pixel list and
+// partial sums are combined with a fixed butterfly, so results do not depend
+// on scheduling.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <math.h>
+
+#include "slf_internal.h"
+
+namespace slf {
+
+__constant__ int kRingDx[8] = {1, 1, 0, -1, -1, -1, 0, 1};
+__constant__ int kRingDy[8] = {0, 1, 1, 1, 0, -1, -1, -1};
+
+// ------------------------------------------------------------------ helpers
+
+// SplitMix64 output function (Steele, Lea, Flood 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+// Inverse depth of sweep level k of superpixel s in view r (Sec. III-B):
+// bin k of width dq starting at qmin, offset by a per-(view, superpixel,
+// level) uniform draw taken from the top 24 bits of mix64.
+__device__ __forceinline__ double level_q(uint64_t seed, int jitter, double qmin, double dq, int r, int s, int k) {
+  double u = 0.0;
+  if (jitter) {
+    uint64_t key = seed ^ ((uint64_t)r << 48) ^ ((uint64_t)s << 24) ^ (uint64_t)k;
+    u = (double)(mix64(key) >> 40) * (1.0 / 16777216.0);
+  }
+  return qmin + ((double)k + u) * dq;
+}
+
+// Butterfly sums: every lane ends with the bitwise-identical total.
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+__device__ __forceinline__ int wave_sum_i(int x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+__device__ __forceinline__ long long wave_sum_ll(long long x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+__device__ __forceinline__ float wave_min(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, kWave));
+  return x;
+}
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, kWave));
+  return x;
+}
+// Sum over lanes 0..7 (other lanes must contribute 0), broadcast to all lanes.
+__device__ __forceinline__ float ring_sum(float x) {
+  x += __shfl_xor(x, 4, kWave);
+  x += __shfl_xor(x, 2, kWave);
+  x += __shfl_xor(x, 1, kWave);
+  return __shfl(x, 0, kWave);
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Lane `l`'s value, uniform over the wave (l must be wave-uniform).
+__device__ __forceinline__ float bcast(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// ------------------------------------------------------------------ image texels
+// A texel (x0, y0) holds the four bilinear taps (x0,y0), (x0+1,y0), (x0,y0+1),
+// (x0+1,y0+1) so that one aligned load fetches a whole bilinear footprint.
+
+size_t quad_bytes(int fmt) { return fmt == SLF_FMT_F32 ? 64 : fmt == SLF_FMT_F16 ? 32 : 16; }
+
+template <int FMT>
+__device__ __forceinline__ void fetch_quad(const void *base, int64_t idx, float (&t)[12]);
+
+template <>
+__device__ __forceinline__ void fetch_quad<SLF_FMT_U8>(const void *base, int64_t idx, float (&t)[12]) {
+  const uint4 q = static_cast<const uint4 *>(base)[idx];
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    t[3 * j + 0] = (float)(w[j] & 255u);
+    t[3 * j + 1] = (float)((w[j] >> 8) & 255u);
+    t[3 * j + 2] = (float)((w[j] >> 16) & 255u);
+  }
+}
+
+template <>
+__device__ __forceinline__ void fetch_quad<SLF_FMT_F16>(const void *base, int64_t idx, float (&t)[12]) {
+  const uint4 *p = static_cast<const uint4 *>(base) + 2 * idx;
+  const uint4 a = p[0], b = p[1];
+  const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    __half2 rg = *reinterpret_cast<const __half2 *>(&w[2 * j]);
+    __half2 ba = *reinterpret_cast<const __half2 *>(&w[2 * j + 1]);
+    t[3 * j + 0] = __low2float(rg);
+    t[3 * j + 1] = __high2float(rg);
+    t[3 * j + 2] = __low2float(ba);
+  }
+}
+
+template <>
+__device__ __forceinline__ void fetch_quad<SLF_FMT_F32>(const void *base, int64_t idx, float (&t)[12]) {
+  const float4 *p = static_cast<const float4 *>(base) + 4 * idx;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float4 c = p[j];
+    t[3 * j + 0] = c.x;
+    t[3 * j + 1] = c.y;
+    t[3 * j + 2] = c.z;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_quads(const uint8_t *rgb, int W, int H, void *quads, int64_t quad_off,
+                                               int fmt) {
+  const int64_t n = (int64_t)(W - 1) * (H - 1);
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int x0 = (int)(idx % (W - 1)), y0 = (int)(idx / (W - 1));
+  const int64_t px[4] = {(int64_t)y0 * W + x0, (int64_t)y0 * W + x0 + 1, (int64_t)(y0 + 1) * W + x0,
+                         (int64_t)(y0 + 1) * W + x0 + 1};
+  if (fmt == SLF_FMT_U8) {
+    uint32_t w[4];
+    for (int j = 0; j < 4; ++j) {
+      const uint8_t *c = rgb + 3 * px[j];
+      w[j] = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
+    }
+    static_cast<uint4 *>(quads)[quad_off + idx] = make_uint4(w[0], w[1], w[2], w[3]);
+  } else if (fmt == SLF_FMT_F16) {
+    uint32_t w[8];
+    for (int j = 0; j < 4; ++j) {
+      const uint8_t *c = rgb + 3 * px[j];
+      __half2 rg = __floats2half2_rn((float)c[0], (float)c[1]);
+      __half2 ba = __floats2half2_rn((float)c[2], 0.f);
+      w[2 * j] = *reinterpret_cast<uint32_t *>(&rg);
+      w[2 * j + 1] = *reinterpret_cast<uint32_t *>(&ba);
+    }
+    uint4 *out = static_cast<uint4 *>(quads) + 2 * (quad_off + idx);
+    out[0] = make_uint4(w[0], w[1], w[2], w[3]);
+    out[1] = make_uint4(w[4], w[5], w[6], w[7]);
+  } else {
+    float4 *out = static_cast<float4 *>(quads) + 4 * (quad_off + idx);
+    for (int j = 0; j < 4; ++j) {
+      const uint8_t *c = rgb + 3 * px[j];
+      out[j] = make_float4((float)c[0], (float)c[1], (float)c[2], 0.f);
+    }
+  }
+}
+
+hipError_t launch_quads(int fmt, const uint8_t *rgb, int64_t, int W, int H, void *quads, int64_t quad_off,
+                        hipStream_t st) {
+  const int64_t n = (int64_t)(W - 1) * (H - 1);
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quads, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rgb, W, H, quads, quad_off, fmt);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ superpixel setup (a1)
+
+__global__ __launch_bounds__(256) void k_sp_reset(const ViewDev *views, int V, int S, int *count, int4 *bbox,
+                                                  int *sp_view, int *err) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) *err = 0;
+  if (g >= S) return;
+  int v = 0;
+  while (v + 1 < V && views[v + 1].sp_off <= g) ++v;
+  sp_view[g] = v;
+  count[g] = 0;
+  bbox[g] = make_int4(INT_MAX, INT_MAX, -1, -1);
+}
+
+// Each horizontal run of equal labels is counted once, by its first pixel.
+__global__ __launch_bounds__(256) void k_sp_count(const int *labels, int W, int H, int K, int sp_off, int *count,
+                                                  int4 *bbox, int *err) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)W * H) return;
+  const int x = (int)(idx % W), y = (int)(idx / W);
+  const int l = labels[idx];
+  if (l < 0 || l >= K) {
+    atomicOr(err, 1);
+    return;
+  }
+  if (x > 0 && labels[idx - 1] == l) return;
+  int len = 1;
+  while (x + len < W && labels[idx + len] == l) ++len;
+  const int g = sp_off + l;
+  int *b = reinterpret_cast<int *>(bbox + g);
+  atomicAdd(count + g, len);
+  atomicMin(b + 0, x);
+  atomicMin(b + 1, y);
+  atomicMax(b + 2, x + len - 1);
+  atomicMax(b + 3, y);
+}
+
+// Exclusive scan of count[0..S) into off[0..S], 4096 items per block.
+constexpr int kScanThreads = 1024, kScanItems = 4;
+
+__device__ int block_excl_scan(int x, int *sh, int *total) {
+  const int t = threadIdx.x;
+  sh[t] = x;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    const int y = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += y;
+    __syncthreads();
+  }
+  const int incl = sh[t];
+  *total = sh[kScanThreads - 1];
+  __syncthreads();
+  return incl - x;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(const int *in, int *out, int *blocksum, int n) {
+  __shared__ int sh[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanThreads * kScanItems + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems], s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = base + j < n ? in[base + j] : 0;
+    s += v[j];
+  }
+  int total;
+  int run = block_excl_scan(s, sh, &total);
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < n) out[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int *blocksum, int nb, int *out_total) {
+  __shared__ int sh[kScanThreads];
+  const int base = threadIdx.x * kScanItems;
+  int v[kScanItems], s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = base + j < nb ? blocksum[base + j] : 0;
+    s += v[j];
+  }
+  int total;
+  int run = block_excl_scan(s, sh, &total);
+  for (int j = 0; j < kScanItems; ++j) {
+    if (base + j < nb) blocksum[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 0) *out_total = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int *out, const int *blocksum, int n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += blocksum[i / (kScanThreads * kScanItems)];
+}
+
+// One wavefront per superpixel scans its bounding box in raster order and
+// appends matching pixels with a ballot prefix, so every pixel list is in
+// raster order and the build is deterministic.  Also computes area,
+// centroid and mean colour (Sec. III-C-1: superpixel colour = mean colour).
+__global__ __launch_bounds__(kBlock) void k_sp_fill(const ViewDev *views, const int *labels, const uint8_t *rgb,
+                                                   int S, const int *sp_view, const int *count, const int4 *bbox,
+                                                   const int *px_off, PixEntry *px, int *area, float2 *centroid,
+                                                   double2 *centroid_d, float4 *colour, int *err) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (g >= S) return;
+  const int v = sp_view[g];
+  const ViewDev &vw = views[v];
+  const int s = g - vw.sp_off;
+  const int cnt = count[g];
+  if (cnt == 0) {
+    if (lane == 0) {
+      area[g] = 0;
+      centroid[g] = make_float2(0.f, 0.f);
+      centroid_d[g] = make_double2(0.0, 0.0);
+      colour[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return;
+  }
+  const int4 box = bbox[g];
+  const int base = px_off[g];
+  const int *lab = labels + vw.pix_off;
+  const uint8_t *img = rgb + 3 * vw.pix_off;
+  int written = 0;
+  long long sx = 0, sy = 0;
+  int sr = 0, sg = 0, sb = 0;
+  for (int y = box.y; y <= box.w; ++y) {
+    for (int x0 = box.x; x0 <= box.z; x0 += kWave) {
+      const int x = x0 + lane;
+      const int64_t pidx = (int64_t)y * vw.W + x;
+      const bool m = x <= box.z && lab[(int64_t)y * vw.W + min(x, box.z)] == s;
+      const uint64_t mask = __ballot(m);
+      if (m) {
+        const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+        const uint8_t *c = img + 3 * pidx;
+        const uint32_t rgba = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
+        if (written + pre < cnt) px[base + written + pre] = make_uint2((uint32_t)x | ((uint32_t)y << 16), rgba);
+        sx += x;
+        sy += y;
+        sr += c[0];
+        sg += c[1];
+        sb += c[2];
+      }
+      written += __popcll(mask);
+    }
+  }
+  sx = wave_sum_ll(sx);
+  sy = wave_sum_ll(sy);
+  sr = wave_sum_i(sr);
+  sg = wave_sum_i(sg);
+  sb = wave_sum_i(sb);
+  if (lane == 0) {
+    if (written != cnt) atomicOr(err, 2);
+    area[g] = cnt;
+    const double n = (double)cnt;
+    centroid_d[g] = make_double2((double)sx / n, (double)sy / n);
+    centroid[g] = make_float2((float)((double)sx / n), (float)((double)sy / n));
+    colour[g] = make_float4((float)(sr / (255.0 * n)), (float)(sg / (255.0 * n)), (float)(sb / (255.0 * n)), 0.f);
+  }
+}
+
+hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V, const int *labels,
+                           const uint8_t *rgb, int S, int *count, int4 *bbox, int *px_off, int *scan_tmp,
+                           PixEntry *px, int *area, float2 *centroid, double2 *centroid_d, float4 *colour,
+                           int *sp_view, int *err, hipStream_t st) {
+  if (S <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sp_reset, dim3((S + 255) / 256), dim3(256), 0, st, views_d, V, S, count, bbox, sp_view, err);
+  for (int v = 0; v < V; ++v) {
+    const ViewDev &vw = views_h[v];
+    const int64_t n = (int64_t)vw.W * vw.H;
+    hipLaunchKernelGGL(k_sp_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, labels + vw.pix_off, vw.W,
+                       vw.H, vw.gw * vw.gh, vw.sp_off, count, bbox, err);
+  }
+  const int per = kScanThreads * kScanItems;
+  const int nb = (S + per - 1) / per;
+  if (nb > per) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(kScanThreads), 0, st, count, px_off, scan_tmp, S);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, scan_tmp, nb, px_off + S);
+  hipLaunchKernelGGL(k_scan_add, dim3((S + 255) / 256), dim3(256), 0, st, px_off, scan_tmp, S);
+  hipLaunchKernelGGL(k_sp_fill, dim3((S + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0, st, views_d,
+                     labels, rgb, S, sp_view, count, bbox, px_off, px, area, centroid, centroid_d, colour, err);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ sweep sample
+// One px-view sample of eq. (1): homogeneous projection (x, y, w), bilinear
+// RGB of the neighbour image, SSD against the reference colour, truncation.
+// Samples behind the camera or outside [0, W-1] x [0, H-1] cost T.  The texel
+// address is clamped into the image whatever the coordinates, so the load is
+// always in bounds and issued unconditionally.
+template <int FMT>
+__device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm1, float Hm1, int Wi, int Hi,
+                                             const void *quads, int64_t qbase, float r0, float g0, float b0,
+                                             float T) {
+  const float rw = rcp(w);
+  const float xs = x * rw, ys = y * rw;
+  const bool in = (w > 0.f) & (xs >= 0.f) & (xs <= Wm1) & (ys >= 0.f) & (ys <= Hm1);
+  const float xc = fminf(fmaxf(xs, 0.f), Wm1), yc = fminf(fmaxf(ys, 0.f), Hm1);
+  const int x0 = max(0, min((int)xc, Wi - 2)), y0 = max(0, min((int)yc, Hi - 2));
+  const float fx = xc - (float)x0, fy = yc - (float)y0;
+  float t[12];
+  fetch_quad<FMT>(quads, qbase + (int64_t)y0 * (Wi - 1) + x0, t);
+  float b[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float top = fmaf(fx, t[3 + c] - t[c], t[c]);
+    const float bot = fmaf(fx, t[9 + c] - t[6 + c], t[6 + c]);
+    b[c] = fmaf(fy, bot - top, top);
+  }
+  const float d0 = r0 - b[0], d1 = g0 - b[1], d2 = b0 - b[2];
+  const float ssd = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+  return in ? fminf(ssd, T) : T;
+}
+
+// ------------------------------------------------------------------ plane sweep (a2-a5)
+// Level-chunked: each lane takes (neighbour view, pixel) pairs of the
+// superpixel; for a pair, a = A p~ is formed once and the KC levels of the
+// chunk give (x, y, w) = a + q_k b (the fronto-parallel plane at inverse
+// depth q_k has inverse-depth row (0, 0, q_k)).  Per-level lane partials are
+// summed by a butterfly and the running argmin keeps the smallest level on
+// ties.
+template <int FMT, int KC>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (g >= a.S) return;
+  const int v = a.sp_view[g];
+  const ViewDev &vw = a.views[v];
+  const int s = g - vw.sp_off;
+  const int A = a.area[g];
+  if (A == 0) {
+    if (lane == 0) {
+      a.planes[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      a.gtab[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      a.cost[g] = 0.f;
+      a.choice[g] = -1;
+      a.margin[g] = 0.f;
+    }
+    return;
+  }
+  const int N = vw.n_pairs;
+  const int P = A * N;
+  const int poff = a.px_off[g];
+  float best = INFINITY, second = INFINITY;
+  int kbest = 0;
+  for (int k0 = 0; k0 < a.levels; k0 += KC) {
+    float q[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) q[j] = (float)level_q(a.seed, a.jitter, a.qmin, a.dq, v, s, k0 + j);
+    float acc[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) acc[j] = 0.f;
+    int iv = 0, p = lane;
+    while (p >= A) {
+      p -= A;
+      ++iv;
+    }
+    int cur = -1;
+    float A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, A5 = 0, A6 = 0, A7 = 0, A8 = 0, bx = 0, by = 0, bw = 0;
+    float Wm1 = 0, Hm1 = 0;
+    int Wi = 2, Hi = 2;
+    int64_t qbase = 0;
+    for (int j = lane; j < P; j += kWave) {
+      if (iv != cur) {
+        const PairDev &pg = a.pairs[vw.pair_off + iv];
+        A0 = pg.A[0]; A1 = pg.A[1]; A2 = pg.A[2];
+        A3 = pg.A[3]; A4 = pg.A[4]; A5 = pg.A[5];
+        A6 = pg.A[6]; A7 = pg.A[7]; A8 = pg.A[8];
+        bx = pg.b[0]; by = pg.b[1]; bw = pg.b[2];
+        const ViewDev &vi = a.views[pg.i];
+        Wi = vi.W;
+        Hi = vi.H;
+        Wm1 = (float)(Wi - 1);
+        Hm1 = (float)(Hi - 1);
+        qbase = vi.quad_off;
+        cur = iv;
+      }
+      const PixEntry e = a.px[poff + p];
+      const float pu = (float)(e.x & 0xffffu), pv = (float)(e.x >> 16);
+      const float r0 = (float)(e.y & 255u), g0 = (float)((e.y >> 8) & 255u), b0 = (float)((e.y >> 16) & 255u);
+      const float ax = fmaf(A0, pu, fmaf(A1, pv, A2));
+      const float ay = fmaf(A3, pu, fmaf(A4, pv, A5));
+      const float aw = fmaf(A6, pu, fmaf(A7, pv, A8));
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi,
+                                    Hi, a.quads, qbase, r0, g0, b0, a.T255);
+      }
+      p += kWave;
+      while (p >= A) {
+        p -= A;
+        ++iv;
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const float C = wave_sum(acc[kk]);
+      if (k0 + kk < a.levels) {
+        if (C < best) {
+          second = best;
+          best = C;
+          kbest = k0 + kk;
+        } else if (C < second) {
+          second = C;
+        }
+      }
+    }
+  }
+  if (lane == 0) {
+    const double qb = level_q(a.seed, a.jitter, a.qmin, a.dq, v, s, kbest);
+    a.planes[g] = make_float4((float)(1.0 / qb), 0.f, 0.f, 1.f);
+    a.gtab[g] = make_float4(0.f, 0.f, (float)qb, 0.f);
+    const float norm = 1.f / ((float)A * (float)N * a.T255);
+    a.cost[g] = best * norm;
+    a.choice[g] = kbest;
+    a.margin[g] = a.levels > 1 ? (second - best) * norm : INFINITY;
+  }
+}
+
+hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st) {
+  const dim3 grid((a.S + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);
+  switch (fmt) {
+    case SLF_FMT_U8: hipLaunchKernelGGL((k_sweep<SLF_FMT_U8, 16>), grid, block, 0, st, a); break;
+    case SLF_FMT_F16: hipLaunchKernelGGL((k_sweep<SLF_FMT_F16, 16>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_sweep<SLF_FMT_F32, 16>), grid, block, 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ refinement (a6-a8)
+
+struct Best {
+  float E, second;
+  double d, nx, ny, nz, delta;
+  int slot, evaluated;
+};
+
+// Per-superpixel data the energy needs, uniform over the wave except the
+// ring fields, which lane j < 8 holds for ring neighbour j.  Geometry that
+// defines candidate planes (rays through centroids, normals) is FP64.
+struct SpCtx {
+  int g, v, s, A, N, poff;
+  int ub, vb;                // centroid rounded to the nearest pixel
+  double rsx, rsy, rsz;      // K_r^-1 (c_s, 1)
+  float4 Cs;                 // mean colour
+  float omega_min;           // min over ring neighbours of omega(C_s, C_j); 1 without neighbours
+  int M;                     // number of non-empty ring neighbours
+  // lane j < 8: ring neighbour j
+  int ring_cell;             // -1 if outside the grid or empty
+  double rrx, rry, rrz;      // K_r^-1 (c_j, 1)
+  double ring_d;             // centroid depth in state A
+  float ring_w;              // omega(C_s, C_j) scaled by 1 / max_j omega (same ratio in eq. 5)
+};
+
+__device__ __forceinline__ double bcast_d(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Energy E = E_c E_s (eqs. 3-11) of the 3D plane n . X = delta in camera r.
+template <int FMT>
+__device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, double nx, double ny, double nz,
+                        double delta) {
+  const int lane = threadIdx.x & (kWave - 1);
+
+  if (a.energy_mode == 1) {  // data-only: -normalised TSSD of this plane
+    const double idl = 1.0 / delta;
+    const double gg[3] = {(nx * vw.Kinv_d[0] + ny * vw.Kinv_d[3] + nz * vw.Kinv_d[6]) * idl,
+                          (nx * vw.Kinv_d[1] + ny * vw.Kinv_d[4] + nz * vw.Kinv_d[7]) * idl,
+                          (nx * vw.Kinv_d[2] + ny * vw.Kinv_d[5] + nz * vw.Kinv_d[8]) * idl};
+    float acc = 0.f;
+    for (int iv = 0; iv < c.N; ++iv) {
+      const PairDev &pg = a.pairs[vw.pair_off + iv];
+      const ViewDev &vi = a.views[pg.i];
+      float H[9];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) H[3 * r + q] = (float)(pg.A_d[3 * r + q] + pg.b_d[r] * gg[q]);
+      for (int p = lane; p < c.A; p += kWave) {
+        const PixEntry e = a.px[c.poff + p];
+        const float pu = (float)(e.x & 0xffffu), pv = (float)(e.x >> 16);
+        acc += tssd_sample<FMT>(fmaf(H[0], pu, fmaf(H[1], pv, H[2])), fmaf(H[3], pu, fmaf(H[4], pv, H[5])),
+                                fmaf(H[6], pu, fmaf(H[7], pv, H[8])), (float)(vi.W - 1), (float)(vi.H - 1), vi.W,
+                                vi.H, a.quads, vi.quad_off, (float)(e.y & 255u), (float)((e.y >> 8) & 255u),
+                                (float)((e.y >> 16) & 255u), a.T255);
+      }
+    }
+    return -wave_sum(acc) / ((float)c.A * (float)c.N * a.T255);
+  }
+
+  // Smoothness, eqs. (5)-(6): this plane extrapolated to neighbour j's centroid
+  float Es = 1.f;
+  if ((a.term_mask & 1u) && c.M > 0) {
+    float num = 0.f, den = 0.f;
+    if (lane < 8 && c.ring_cell >= 0) {
+      const double t = nx * c.rrx + ny * c.rry + nz * c.rrz;
+      float sj = 0.f;
+      if (t > 0.0) {
+        const float dd = (float)(c.ring_d - delta / t);
+        sj = __expf(-dd * dd * a.inv2sig2);
+      }
+      num = c.ring_w * sj;
+      den = c.ring_w;
+    }
+    Es = ring_sum(num) / ring_sum(den);
+  }
+
+  // Consistency, eqs. (8)-(11).  Pixels are taken relative to the rounded
+  // centroid (ub, vb) and projections relative to the integer pixel (X0, Y0)
+  // nearest to the projected centroid, so the FP32 per-sample arithmetic
+  // works on small offsets and the nearest-pixel decision of eq. (9) keeps
+  // ~1e-6 px accuracy at any image size.  The per-(candidate, view)
+  // constants are composed in FP64 (lane j composes neighbour view j) and
+  // broadcast with readlane.
+  float Ec = 1.f;
+  if (a.term_mask & 2u) {
+    const double idl = 1.0 / delta;
+    const double gd0 = (nx * vw.Kinv_d[0] + ny * vw.Kinv_d[3] + nz * vw.Kinv_d[6]) * idl;
+    const double gd1 = (nx * vw.Kinv_d[1] + ny * vw.Kinv_d[4] + nz * vw.Kinv_d[7]) * idl;
+    const double gd2 = (nx * vw.Kinv_d[2] + ny * vw.Kinv_d[5] + nz * vw.Kinv_d[8]) * idl;
+    const float i0 = (float)(gd0 * c.ub + gd1 * c.vb + gd2);  // 1 / D at the rounded centroid
+    const float gu = (float)gd0, gv = (float)gd1;
+    float sum = 0.f;
+    const float occ = (a.term_mask & 4u) ? a.eta * (1.f - c.omega_min) : 0.f;
+    const float tol = 1.f + a.occ_tol;
+    for (int base = 0; base < c.N; base += kWave) {
+      // lane j: constants of neighbour view base + j
+      float ax = 0.f, axu = 0.f, axv = 0.f, ay = 0.f, ayu = 0.f, ayv = 0.f, aw = 0.f, awu = 0.f, awv = 0.f;
+      int X0 = 0, Y0 = 0;
+      if (base + lane < c.N) {
+        const PairDev &pg = a.pairs[vw.pair_off + base + lane];
+        double H[9];
+        const double gg[3] = {gd0, gd1, gd2};
+        for (int r = 0; r < 3; ++r)
+          for (int q = 0; q < 3; ++q) H[3 * r + q] = pg.A_d[3 * r + q] + pg.b_d[r] * gg[q];
+        const double hx = H[0] * c.ub + H[1] * c.vb + H[2];
+        const double hy = H[3] * c.ub + H[4] * c.vb + H[5];
+        const double hw = H[6] * c.ub + H[7] * c.vb + H[8];
+        if (hw > 0.0) {
+          const double xc = hx / hw, yc = hy / hw;
+          if (fabs(xc) < 1.0e7 && fabs(yc) < 1.0e7) {
+            X0 = (int)floor(xc + 0.5);
+            Y0 = (int)floor(yc + 0.5);
+          }
+        }
+        ax = (float)(hx - X0 * hw);
+        axu = (float)(H[0] - X0 * H[6]);
+        axv = (float)(H[1] - X0 * H[7]);
+        ay = (float)(hy - Y0 * hw);
+        ayu = (float)(H[3] - Y0 * H[6]);
+        ayv = (float)(H[4] - Y0 * H[7]);
+        aw = (float)hw;
+        awu = (float)H[6];
+        awv = (float)H[7];
+      }
+      const int nv = min(kWave, c.N - base);
+      for (int jv = 0; jv < nv; ++jv) {
+        const float bax = bcast(ax, jv), baxu = bcast(axu, jv), baxv = bcast(axv, jv);
+        const float bay = bcast(ay, jv), bayu = bcast(ayu, jv), bayv = bcast(ayv, jv);
+        const float baw = bcast(aw, jv), bawu = bcast(awu, jv), bawv = bcast(awv, jv);
+        const int bX0 = __builtin_amdgcn_readlane(X0, jv), bY0 = __builtin_amdgcn_readlane(Y0, jv);
+        const PairDev &pg = a.pairs[vw.pair_off + base + jv];
+        const ViewDev &vi = a.views[pg.i];
+        const float Wm1 = (float)(vi.W - 1), Hm1 = (float)(vi.H - 1);
+        const float fX0 = (float)bX0, fY0 = (float)bY0;
+        const int *lab = a.labels + vi.pix_off;
+        const int Ki = vi.gw * vi.gh;
+        float sw = 0.f, gx = 0.f;
+        int nX = 0;
+        bool anyY = false;
+        for (int p = lane; p < c.A; p += kWave) {
+          const PixEntry e = a.px[c.poff + p];
+          const float du = (float)((int)(e.x & 0xffffu) - c.ub), dv = (float)((int)(e.x >> 16) - c.vb);
+          const float iota = fmaf(gu, du, fmaf(gv, dv, i0));  // 1 / D(p)
+          if (!(iota > 0.f)) continue;
+          const float w = fmaf(bawu, du, fmaf(bawv, dv, baw));
+          if (!(w > 0.f)) continue;
+          const float rw = rcp(w);
+          const float dx = fmaf(baxu, du, fmaf(baxv, dv, bax)) * rw;
+          const float dy = fmaf(bayu, du, fmaf(bayv, dv, bay)) * rw;
+          const float z = w * rcp(iota);  // depth of P in camera i
+          const float uf = fX0 + floorf(dx + 0.5f), vf = fY0 + floorf(dy + 0.5f);
+          if (!(uf >= 0.f && uf <= Wm1 && vf >= 0.f && vf <= Hm1)) continue;
+          int l = lab[(int64_t)vf * vi.W + (int64_t)uf];
+          l = min(max(l, 0), Ki - 1);
+          const int gl = vi.sp_off + l;
+          const float4 Cl = a.colour[gl];
+          const float4 gt = a.gtabA[gl];
+          const float dr = c.Cs.x - Cl.x, dg = c.Cs.y - Cl.y, db = c.Cs.z - Cl.z;
+          sw += __expf(-fmaf(db, db, fmaf(dg, dg, dr * dr)) * a.inv2alpha2);
+          const float den = fmaf(gt.x, fX0 + dx, fmaf(gt.y, fY0 + dy, gt.z));
+          if (den > 0.f) {
+            const float Di = rcp(den);
+            if (z <= Di * tol) {
+              ++nX;
+              const float dz = z - Di;
+              gx += __expf(-dz * dz * a.inv2sig2);
+            } else {
+              anyY = true;
+            }
+          } else {
+            ++nX;  // D(p^i) = +inf: visible, zero agreement
+          }
+        }
+        sw = wave_sum(sw);
+        gx = wave_sum(gx);
+        nX = wave_sum_i(nX);
+        const bool Y = __ballot(anyY) != 0ull;
+        const float Si = sw / (float)c.A;
+        const float Vi = nX > 0 ? Si * gx / (float)nX : 0.f;
+        sum += Vi + (Y ? occ : 0.f);
+      }
+    }
+    Ec = sum / (float)c.N;
+  }
+  return Ec * Es;
+}
+
+template <int FMT>
+__device__ __forceinline__ void consider(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, Best &b, double nx,
+                                         double ny, double nz, double delta, int slot) {
+  const double tt = nx * c.rsx + ny * c.rsy + nz * c.rsz;
+  if (!(tt > 0.0) || !(delta > 0.0)) return;  // not in front of camera r at this centroid
+  const float E = energy<FMT>(a, c, vw, nx, ny, nz, delta);
+  ++b.evaluated;
+  if (b.slot < 0 || E > b.E) {
+    if (b.slot >= 0) b.second = b.E;
+    b.E = E;
+    b.slot = slot;
+    b.d = delta / tt;
+    b.nx = nx;
+    b.ny = ny;
+    b.nz = nz;
+    b.delta = delta;
+  } else if (E > b.second) {
+    b.second = E;
+  }
+}
+
+__device__ __forceinline__ void ray_of(const ViewDev &vw, double2 cp, double &x, double &y, double &z) {
+  x = vw.Kinv_d[0] * cp.x + vw.Kinv_d[1] * cp.y + vw.Kinv_d[2];
+  y = vw.Kinv_d[3] * cp.x + vw.Kinv_d[4] * cp.y + vw.Kinv_d[5];
+  z = vw.Kinv_d[6] * cp.x + vw.Kinv_d[7] * cp.y + vw.Kinv_d[8];
+}
+
+// Candidate from the stored plane of cell k of the same view (same 3D plane).
+template <int FMT>
+__device__ __forceinline__ void consider_cell(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, Best &b,
+                                              int k, int slot) {
+  const int gk = vw.sp_off + k;
+  const float4 pk = a.planesA[gk];
+  double rx, ry, rz;
+  ray_of(vw, a.centroid_d[gk], rx, ry, rz);
+  const double nx = pk.y, ny = pk.z, nz = pk.w;
+  consider<FMT>(a, c, vw, b, nx, ny, nz, (double)pk.x * (nx * rx + ny * ry + nz * rz), slot);
+}
+
+// One refinement step per superpixel (Sec. III-C): propagation over the
+// kernel, then 8 triangle normals pivoting at the winner's centroid depth.
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (g >= a.S) return;
+  SpCtx c;
+  c.g = g;
+  c.v = a.sp_view[g];
+  const ViewDev &vw = a.views[c.v];
+  c.s = g - vw.sp_off;
+  c.A = a.area[g];
+  if (c.A == 0) {
+    if (lane == 0) {
+      a.planesB[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      a.gtabB[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      a.energy[g] = 0.f;
+      a.choice[g] = -1;
+      a.margin[g] = 0.f;
+    }
+    return;
+  }
+  c.N = vw.n_pairs;
+  c.poff = a.px_off[g];
+  const double2 cs = a.centroid_d[g];
+  ray_of(vw, cs, c.rsx, c.rsy, c.rsz);
+  c.Cs = a.colour[g];
+  c.ub = (int)floor(cs.x + 0.5);
+  c.vb = (int)floor(cs.y + 0.5);
+  const int gx = c.s % vw.gw, gy = c.s / vw.gw;
+
+  // ring neighbour j on lane j
+  c.ring_cell = -1;
+  c.rrx = c.rry = c.rrz = 0.0;
+  c.ring_d = 0.0;
+  float dist2 = INFINITY;
+  if (lane < 8) {
+    const int x = gx + kRingDx[lane], y = gy + kRingDy[lane];
+    if (x >= 0 && x < vw.gw && y >= 0 && y < vw.gh) {
+      const int k = y * vw.gw + x;
+      const int gk = vw.sp_off + k;
+      if (a.area[gk] > 0) {
+        c.ring_cell = k;
+        ray_of(vw, a.centroid_d[gk], c.rrx, c.rry, c.rrz);
+        c.ring_d = a.planesA[gk].x;
+        const float4 Ck = a.colour[gk];
+        const float dr = c.Cs.x - Ck.x, dg = c.Cs.y - Ck.y, db = c.Cs.z - Ck.z;
+        dist2 = dr * dr + dg * dg + db * db;
+      }
+    }
+  }
+  c.M = __popcll(__ballot(c.ring_cell >= 0));
+  const float dmin2 = wave_min(dist2);
+  const float dmax2 = wave_max(c.ring_cell >= 0 ? dist2 : -INFINITY);
+  c.ring_w = c.ring_cell >= 0 ? __expf(-(dist2 - dmin2) * a.inv2alpha2) : 0.f;
+  c.omega_min = c.M > 0 ? __expf(-dmax2 * a.inv2alpha2) : 1.f;
+
+  Best b;
+  b.E = -INFINITY;
+  b.second = -INFINITY;
+  b.slot = -1;
+  b.evaluated = 0;
+  b.d = b.nx = b.ny = b.nz = b.delta = 0.0;
+
+  // propagation: current plane, ring, far star
+  consider_cell<FMT>(a, c, vw, b, c.s, 0);
+  for (int j = 0; j < 8; ++j) {
+    const int k = __builtin_amdgcn_readlane(c.ring_cell, j);
+    if (k >= 0) consider_cell<FMT>(a, c, vw, b, k, 1 + j);
+  }
+  const int R = vw.kr_init / a.iter;
+  for (int m = a.kernel_step; m <= R; m += a.kernel_step) {
+    for (int j = 0; j < 8; ++j) {
+      const int x = gx + m * kRingDx[j], y = gy + m * kRingDy[j];
+      if (x < 0 || x >= vw.gw || y < 0 || y >= vw.gh) continue;
+      const int k = y * vw.gw + x;
+      if (a.area[vw.sp_off + k] <= 0) continue;
+      consider_cell<FMT>(a, c, vw, b, k, 9 + 8 * (m / a.kernel_step - 1) + j);
+    }
+  }
+
+  // triangle normals (Sec. III-C): plane through X_s (winner's depth) and the
+  // 3D centroids of ring neighbours j, j+1 at their depths in A, in FP64
+  if (b.slot >= 0) {
+    const double Xs0 = b.d * c.rsx, Xs1 = b.d * c.rsy, Xs2 = b.d * c.rsz;
+    for (int j = 0; j < 8; ++j) {
+      const int j2 = (j + 1) & 7;
+      const int ka = __builtin_amdgcn_readlane(c.ring_cell, j), kb = __builtin_amdgcn_readlane(c.ring_cell, j2);
+      if (ka < 0 || kb < 0) continue;
+      const double da = bcast_d(c.ring_d, j), dbb = bcast_d(c.ring_d, j2);
+      const double ea0 = da * bcast_d(c.rrx, j) - Xs0, ea1 = da * bcast_d(c.rry, j) - Xs1,
+                   ea2 = da * bcast_d(c.rrz, j) - Xs2;
+      const double eb0 = dbb * bcast_d(c.rrx, j2) - Xs0, eb1 = dbb * bcast_d(c.rry, j2) - Xs1,
+                   eb2 = dbb * bcast_d(c.rrz, j2) - Xs2;
+      double n0 = ea1 * eb2 - ea2 * eb1;
+      double n1 = ea2 * eb0 - ea0 * eb2;
+      double n2 = ea0 * eb1 - ea1 * eb0;
+      const double len = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+      const double la = sqrt(ea0 * ea0 + ea1 * ea1 + ea2 * ea2), lb = sqrt(eb0 * eb0 + eb1 * eb1 + eb2 * eb2);
+      if (!(len > 1e-12 * la * lb)) continue;
+      n0 /= len;
+      n1 /= len;
+      n2 /= len;
+      if (n0 * c.rsx + n1 * c.rsy + n2 * c.rsz < 0.0) {
+        n0 = -n0;
+        n1 = -n1;
+        n2 = -n2;
+      }
+      consider<FMT>(a, c, vw, b, n0, n1, n2, n0 * Xs0 + n1 * Xs1 + n2 * Xs2, 1000 + j);
+    }
+  }
+
+  if (lane == 0) {
+    if (b.slot < 0) {  // no valid candidate: keep the current plane
+      a.planesB[g] = a.planesA[g];
+      a.gtabB[g] = a.gtabA[g];
+      a.energy[g] = -INFINITY;
+      a.choice[g] = -1;
+      a.margin[g] = 0.f;
+    } else {
+      a.planesB[g] = make_float4((float)b.d, (float)b.nx, (float)b.ny, (float)b.nz);
+      const double id = 1.0 / b.delta;
+      a.gtabB[g] = make_float4((float)((b.nx * vw.Kinv_d[0] + b.ny * vw.Kinv_d[3] + b.nz * vw.Kinv_d[6]) * id),
+                               (float)((b.nx * vw.Kinv_d[1] + b.ny * vw.Kinv_d[4] + b.nz * vw.Kinv_d[7]) * id),
+                               (float)((b.nx * vw.Kinv_d[2] + b.ny * vw.Kinv_d[5] + b.nz * vw.Kinv_d[8]) * id), 0.f);
+      a.energy[g] = b.E;
+      a.choice[g] = b.slot;
+      a.margin[g] = b.evaluated > 1 ? b.E - b.second : INFINITY;
+    }
+    atomicAdd(&a.work[0], (unsigned long long)b.evaluated);
+    atomicAdd(&a.work[1], (unsigned long long)b.evaluated * (unsigned long long)c.A * (unsigned long long)c.N);
+  }
+}
+
+hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st) {
+  const dim3 grid((a.S + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);
+  switch (fmt) {
+    case SLF_FMT_U8: hipLaunchKernelGGL((k_refine<SLF_FMT_U8>), grid, block, 0, st, a); break;
+    case SLF_FMT_F16: hipLaunchKernelGGL((k_refine<SLF_FMT_F16>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_refine<SLF_FMT_F32>), grid, block, 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ depth readout (a9)
+// D(p) = 1 / (g_s . p~) for s = label(p), 0 where the plane does not face the camera.
+__global__ __launch_bounds__(256) void k_depth(const int *labels, int W, int H, int K, int sp_off, const float4 *gtab,
+                                               float *out, int64_t stride) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)W * H) return;
+  const int x = (int)(idx % W), y = (int)(idx / W);
+  int l = labels[idx];
+  l = min(max(l, 0), K - 1);
+  const float4 gt = gtab[sp_off + l];
+  const float den = fmaf(gt.x, (float)x, fmaf(gt.y, (float)y, gt.z));
+  out[(int64_t)y * stride + x] = den > 0.f ? 1.f / den : 0.f;
+}
+
+hipError_t launch_depth(const ViewDev *, const ViewDev &vh, int, const int *labels, const float4 *gtab, float *out,
+                        int64_t stride, hipStream_t st) {
+  const int64_t n = (int64_t)vh.W * vh.H;
+  hipLaunchKernelGGL(k_depth, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, labels + vh.pix_off, vh.W, vh.H,
+                     vh.gw * vh.gh, vh.sp_off, gtab, out, stride);
+  return hipGetLastError();
+}
+
+}  // namespace slf

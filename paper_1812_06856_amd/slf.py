@@ -1,0 +1,255 @@
+"""Python binding of libslf (include/slf.h): argument marshalling only.
+
+Every step of the depth path runs in the HIP library.  torch is imported
+first so that the library binds to the HIP runtime torch already loaded (one
+runtime per process); torch supplies device memory and streams only.  If the
+built library is missing, loading fails loudly: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading libslf: shared HIP runtime)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libslf.so")
+
+SLF_OK, SLF_EINVAL, SLF_ESTATE, SLF_ENOMEM, SLF_EDEVICE, SLF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SLF_IMAGE_U8, SLF_IMAGE_F16, SLF_IMAGE_F32 = 0, 1, 2
+
+EXPORTED = [
+    "slf_default_params", "slf_create", "slf_destroy", "slf_set_stream", "slf_set_params", "slf_set_cameras",
+    "slf_set_neighbors", "slf_set_image_rgb8", "slf_set_labels", "slf_prepare", "slf_sweep", "slf_set_planes", "slf_propagate",
+    "slf_get_planes", "slf_get_depth", "slf_get_superpixels", "slf_get_work", "slf_reset_work", "slf_synchronize",
+    "slf_status_string", "slf_last_error",
+]
+
+
+class slf_params(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("levels", ctypes.c_int32), ("d_min", ctypes.c_double),
+                ("d_max", ctypes.c_double), ("seed", ctypes.c_uint64), ("jitter", ctypes.c_int32),
+                ("tssd_T", ctypes.c_float), ("sigma", ctypes.c_float), ("alpha", ctypes.c_float),
+                ("eta", ctypes.c_float), ("occ_tol", ctypes.c_float), ("kernel_step", ctypes.c_int32),
+                ("kernel_radius_init", ctypes.c_int32), ("term_mask", ctypes.c_uint32),
+                ("image_precision", ctypes.c_int32), ("homography_fp64", ctypes.c_int32),
+                ("energy_mode", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libslf.so and declares the ABI; raises if the library was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libslf.so not found at %s: build it first (paper_1812_06856_amd/build.py)" % path)
+    L = ctypes.CDLL(path)
+    P, I, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    L.slf_default_params.argtypes = [ctypes.POINTER(slf_params)]
+    L.slf_default_params.restype = None
+    L.slf_create.argtypes = [I, ctypes.POINTER(P)]
+    L.slf_destroy.argtypes = [P]
+    L.slf_set_stream.argtypes = [P, P]
+    L.slf_set_params.argtypes = [P, ctypes.POINTER(slf_params)]
+    L.slf_set_cameras.argtypes = [P, I, P, P, P, P]
+    L.slf_set_neighbors.argtypes = [P, I, I, P]
+    L.slf_set_image_rgb8.argtypes = [P, I, P, I64, I]
+    L.slf_set_labels.argtypes = [P, I, P, I64, I, I, I]
+    L.slf_prepare.argtypes = [P]
+    L.slf_sweep.argtypes = [P]
+    L.slf_set_planes.argtypes = [P, I, P]
+    L.slf_propagate.argtypes = [P, I, I]
+    L.slf_get_planes.argtypes = [P, I, P, P, P, P]
+    L.slf_get_depth.argtypes = [P, I, P, I64, I]
+    L.slf_get_superpixels.argtypes = [P, I, P, P, P]
+    L.slf_get_work.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+    L.slf_reset_work.argtypes = [P]
+    L.slf_synchronize.argtypes = [P]
+    L.slf_status_string.argtypes = [I]
+    L.slf_status_string.restype = ctypes.c_char_p
+    L.slf_last_error.argtypes = [P]
+    L.slf_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        getattr(L, name)  # every declared entry point must be exported
+    _lib = L
+    return L
+
+
+class SlfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (_status_name(status), status, msg))
+        self.status = status
+
+
+def _status_name(s):
+    return {0: "SLF_OK", -1: "SLF_EINVAL", -2: "SLF_ESTATE", -3: "SLF_ENOMEM", -4: "SLF_EDEVICE",
+            -5: "SLF_EUNSUPPORTED"}.get(s, "?")
+
+
+def _ptr(a):
+    if isinstance(a, torch.Tensor):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_params(**overrides) -> slf_params:
+    p = slf_params()
+    load().slf_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def params_from(mp, **overrides) -> slf_params:
+    """slf_params from any object/dict with the method parameter names."""
+    g = mp if isinstance(mp, dict) else mp.as_dict()
+    names = [f[0] for f in slf_params._fields_]
+    kw = {k: g[k] for k in names if k in g}
+    kw.update(overrides)
+    return default_params(**kw)
+
+
+class Context:
+    """One slf context on a HIP device; methods mirror the C calls."""
+
+    def __init__(self, device: int = 0):
+        self._L = load()
+        h = ctypes.c_void_p()
+        self._check(self._L.slf_create(device, ctypes.byref(h)), ctx=None)
+        self._h = h
+        self.device = device
+        self.dims = []
+        self.grids = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.slf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, ctx="self"):
+        if rc != SLF_OK:
+            msg = self._L.slf_last_error(self._h).decode() if ctx == "self" and self._h else ""
+            raise SlfError(rc, msg)
+        return rc
+
+    def last_error(self) -> str:
+        return self._L.slf_last_error(self._h).decode()
+
+    # -- configuration
+    def set_stream(self, stream) -> None:
+        ptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        self._check(self._L.slf_set_stream(self._h, ctypes.c_void_p(ptr)))
+
+    def set_params(self, p: slf_params) -> None:
+        self._check(self._L.slf_set_params(self._h, ctypes.byref(p)))
+
+    def set_cameras(self, wh, K, R, t) -> None:
+        wh = np.ascontiguousarray(wh, np.int32).reshape(-1, 2)
+        K = np.ascontiguousarray(K, np.float64).reshape(-1, 9)
+        R = np.ascontiguousarray(R, np.float64).reshape(-1, 9)
+        t = np.ascontiguousarray(t, np.float64).reshape(-1, 3)
+        self._check(self._L.slf_set_cameras(self._h, wh.shape[0], _ptr(wh), _ptr(K), _ptr(R), _ptr(t)))
+        self.dims = [tuple(x) for x in wh.tolist()]
+        self.grids = [None] * wh.shape[0]
+
+    def set_neighbors(self, view: int, views: Sequence[int]) -> None:
+        a = np.ascontiguousarray(views, np.int32)
+        self._check(self._L.slf_set_neighbors(self._h, view, a.size, _ptr(a)))
+
+    def set_image(self, view: int, rgb) -> None:
+        """rgb: (H, W, 3) uint8 numpy array (host) or torch uint8 tensor on the device."""
+        if isinstance(rgb, torch.Tensor) and rgb.is_cuda:
+            assert rgb.dtype == torch.uint8 and rgb.dim() == 3 and rgb.stride(2) == 1 and rgb.stride(1) == 3
+            self._check(self._L.slf_set_image_rgb8(self._h, view, _ptr(rgb), rgb.stride(0), 1))
+        else:
+            a = np.ascontiguousarray(rgb, np.uint8)
+            self._check(self._L.slf_set_image_rgb8(self._h, view, _ptr(a), a.strides[0], 0))
+
+    def set_labels(self, view: int, labels, grid_w: int, grid_h: int) -> None:
+        if isinstance(labels, torch.Tensor) and labels.is_cuda:
+            assert labels.dtype == torch.int32 and labels.dim() == 2 and labels.stride(1) == 1
+            self._check(self._L.slf_set_labels(self._h, view, _ptr(labels), labels.stride(0), grid_w, grid_h, 1))
+        else:
+            a = np.ascontiguousarray(labels, np.int32)
+            self._check(self._L.slf_set_labels(self._h, view, _ptr(a), a.shape[1], grid_w, grid_h, 0))
+        self.grids[view] = (grid_w, grid_h)
+
+    def load_rig(self, rig, params=None) -> None:
+        """Cameras, neighbour lists, images and labels of an input rig (host arrays)."""
+        vs = rig.views
+        self.set_cameras([(v.W, v.H) for v in vs], [v.K for v in vs], [v.R for v in vs], [v.t for v in vs])
+        if params is not None:
+            self.set_params(params)
+        if rig.neighbors is not None:
+            for r, nb in enumerate(rig.neighbor_lists()):
+                self.set_neighbors(r, nb)
+        for i, v in enumerate(vs):
+            self.set_image(i, v.rgb)
+            self.set_labels(i, v.labels, v.gw, v.gh)
+
+    # -- the path
+    def prepare(self) -> None:
+        self._check(self._L.slf_prepare(self._h))
+
+    def sweep(self) -> None:
+        self._check(self._L.slf_sweep(self._h))
+
+    def set_planes(self, view: int, planes) -> None:
+        a = np.ascontiguousarray(planes, np.float32).reshape(-1, 4)
+        self._check(self._L.slf_set_planes(self._h, view, _ptr(a)))
+
+    def propagate(self, first_iter: int, n_iters: int) -> None:
+        self._check(self._L.slf_propagate(self._h, first_iter, n_iters))
+
+    def get_planes(self, view: int):
+        gw, gh = self.grids[view]
+        K = gw * gh
+        planes = np.empty((K, 4), np.float32)
+        e = np.empty(K, np.float32)
+        ch = np.empty(K, np.int32)
+        mg = np.empty(K, np.float32)
+        self._check(self._L.slf_get_planes(self._h, view, _ptr(planes), _ptr(e), _ptr(ch), _ptr(mg)))
+        return planes, e, ch, mg
+
+    def get_depth(self, view: int, out: Optional[torch.Tensor] = None):
+        W, H = self.dims[view]
+        if out is not None:
+            assert out.is_cuda and out.dtype == torch.float32 and out.stride(1) == 1
+            self._check(self._L.slf_get_depth(self._h, view, _ptr(out), out.stride(0), 1))
+            return out
+        a = np.empty((H, W), np.float32)
+        self._check(self._L.slf_get_depth(self._h, view, _ptr(a), W, 0))
+        return a
+
+    def get_superpixels(self, view: int):
+        gw, gh = self.grids[view]
+        K = gw * gh
+        area = np.empty(K, np.int32)
+        cen = np.empty((K, 2), np.float32)
+        col = np.empty((K, 3), np.float32)
+        self._check(self._L.slf_get_superpixels(self._h, view, _ptr(area), _ptr(cen), _ptr(col)))
+        return area, cen, col
+
+    def work(self):
+        e, s = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self._L.slf_get_work(self._h, ctypes.byref(e), ctypes.byref(s)))
+        return int(e.value), int(s.value)
+
+    def reset_work(self) -> None:
+        self._check(self._L.slf_reset_work(self._h))
+
+    def synchronize(self) -> None:
+        self._check(self._L.slf_synchronize(self._h))

@@ -1,0 +1,109 @@
+"""Full-size parity (8 views, 1920x1080, 5974 superpixels per view, 256 levels)
+in the launch configuration the benchmark times, on sampled superpixels the
+oracle computes one by one, plus properties that hold at any size."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from lfsynth import config2, random_planes
+from oracle.oracle import Oracle
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def full():
+    from paper_1812_06856_amd import slf
+
+    _say("generating the full-HD 8-view workload")
+    w = config2()
+    ctx = slf.Context(0)
+    ctx.load_rig(w.rig, slf.params_from(w.params))
+    orc = Oracle(w.rig, w.params)
+    return w, ctx, orc
+
+
+def _sample(orc, n, seed):
+    rng = np.random.default_rng(seed)
+    area = orc.sp_stats()[0]
+    out = []
+    while len(out) < n:
+        v = int(rng.integers(0, orc.V))
+        s = int(rng.integers(0, orc.sp_off[v + 1] - orc.sp_off[v]))
+        if area[orc.sp_off[v] + s] > 0:
+            out.append((v, s))
+    # plus corner and edge cells, where warps leave the image
+    for v in (0, orc.V - 1):
+        gw = 103
+        for s in (0, gw - 1, 57 * gw, 58 * gw - 1, 29 * gw):
+            out.append((v, s))
+    return out
+
+
+def test_fullsize_sweep_sampled(full):
+    w, ctx, orc = full
+    _say("full-size sweep")
+    ctx.sweep()
+    ctx.synchronize()
+    rep = parity.check_sweep(orc, ctx, sample=_sample(orc, 40, 1))
+    _say("full-size sweep parity: %s" % {k: (v if k != "bad" else v[:5]) for k, v in rep.items()})
+    assert not rep["bad"]
+
+
+def test_fullsize_refine_first_iteration_sampled(full):
+    """Iteration 1 (57 candidates: widest kernel) from a given seeded state."""
+    w, ctx, orc = full
+    _say("full-size refine iteration 1 from a seeded state")
+    rng = np.random.default_rng(21)
+    A64 = parity.round_state(np.concatenate([random_planes(rng, v.gw, v.gh, 1.9, 8.6) for v in w.rig.views]))
+    for v in range(orc.V):
+        ctx.set_planes(v, A64[orc.view_slice(v)])
+    ctx.propagate(1, 1)
+    rep = parity.check_refine(orc, ctx, A64, 1, sample=_sample(orc, 40, 2))
+    _say("full-size refine parity: %s" % {k: (v if k != "bad" else v[:5]) for k, v in rep.items()})
+    assert not rep["bad"]
+    # depth readout of the given state at sampled pixels
+    for v in (0, 5):
+        D_o = orc.render_depth(A64, v)
+        ctx.set_planes(v, A64[orc.view_slice(v)])
+        D_g = ctx.get_depth(v)
+        assert np.allclose(D_g, D_o, rtol=2e-5, atol=0)
+
+
+def test_fullsize_pipeline_properties(full):
+    """Sweep + 8 iterations as timed by the benchmark: outputs are well formed,
+    energies lie in [0, 1.5], slot indices follow the kernel schedule, the
+    mean energy does not decrease, and the work counters match the schedule."""
+    w, ctx, orc = full
+    _say("full-size pipeline sweep + 8 iterations")
+    area = orc.sp_stats()[0]
+    ctx.reset_work()
+    ctx.sweep()
+    ev0, sm0 = ctx.work()
+    n_nonempty = int((area > 0).sum())
+    assert ev0 == n_nonempty * 256
+    means = []
+    for it in range(1, 9):
+        ctx.propagate(it, 1)
+        P, E, K, M = parity.gpu_state(ctx, orc.V)
+        ok = area > 0
+        assert np.all(np.isfinite(P[ok])) and np.all(P[ok, 0] > 0)
+        assert np.allclose(np.linalg.norm(P[ok, 1:], axis=1), 1, atol=1e-5)
+        assert np.all((E[ok] >= 0) & (E[ok] <= 1.5 + 1e-6))
+        R = orc.kernel_radius(0, it)
+        far_max = 9 + 8 * (R // 5 - 1) + 7 if R >= 5 else 8
+        assert np.all((K[ok] >= 0) & ((K[ok] <= far_max) | ((K[ok] >= 1000) & (K[ok] < 1008))))
+        assert np.all(K[~ok] == -1)
+        means.append(float(E[ok].mean()))
+    _say("mean energy per iteration: %s" % means)
+    assert means[-1] >= means[0]
+    ev, sm = ctx.work()
+    assert ev > ev0 and sm > sm0
+    D = ctx.get_depth(0)
+    assert D.shape == (1080, 1920) and np.all(D > 0)

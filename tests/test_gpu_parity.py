@@ -1,0 +1,329 @@
+"""GPU (HIP, through the C ABI) vs FP64 oracle parity on seeded synthetic inputs."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from lfsynth import config1, tiny_custom
+from lfsynth.rig import line_rig, grid_rig
+from lfsynth.scene import make_scene, build_rig, grid_labels
+from oracle.oracle import Oracle
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(workload, **over):
+    from paper_1812_06856_amd import slf
+
+    ctx = slf.Context(0)
+    p = slf.params_from(workload.params, **over)
+    ctx.load_rig(workload.rig, p)
+    return ctx
+
+
+def _oracle(workload, **over):
+    p = workload.params
+    for k, v in over.items():
+        setattr(p, k, v)
+    return Oracle(workload.rig, p)
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _assert_clean(rep, what):
+    _say("%s: %s" % (what, {k: (v if k != "bad" else len(v)) for k, v in rep.items()}))
+    assert not rep["bad"], rep["bad"][:10]
+
+
+def _lockstep(w, iters, ctx=None, orc=None, **over):
+    ctx = ctx or _ctx(w, **over)
+    orc = orc or _oracle(w, **over)
+    A = orc.sweep()[0]
+    for it in range(1, iters + 1):
+        A64 = parity.round_state(A)
+        for v in range(orc.V):
+            ctx.set_planes(v, A64[orc.view_slice(v)])
+        ctx.propagate(it, 1)
+        B, E, K, M = orc.refine(A64, it)
+        rep = parity.check_refine(orc, ctx, A64, it, B, E, K, M)
+        _assert_clean(rep, "%s refine iter %d" % (w.name, it))
+        A = B
+    return ctx, orc
+
+
+# ------------------------------------------------------------------ a1: superpixel setup
+
+@pytest.mark.parametrize("case", ["config1", "ragged161x117", "holes"])
+def test_superpixel_statistics(case):
+    _say("superpixels: %s" % case)
+    if case == "config1":
+        w = config1()
+    elif case == "ragged161x117":
+        w = tiny_custom(161, 117, 13, 9, seed=3)
+    else:
+        w = tiny_custom(96, 64, 8, 6, seed=4, labels="grid")
+        for v in w.rig.views:
+            v.labels[v.labels == 9] = 10
+            v.labels[v.labels == 30] = 22
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    ctx.sweep()
+    area_o, cen_o, col_o = orc.sp_stats()
+    for v in range(orc.V):
+        sl = orc.view_slice(v)
+        area, cen, col = ctx.get_superpixels(v)
+        assert np.array_equal(area, area_o[sl])
+        assert np.allclose(cen, cen_o[sl], rtol=0, atol=2e-4)
+        assert np.allclose(col, col_o[sl], rtol=0, atol=1e-6)
+
+
+# ------------------------------------------------------------------ a2-a5: sweep
+
+@pytest.mark.parametrize("fmt", [0, 1, 2])
+def test_sweep_parity_tiny(fmt):
+    _say("sweep parity tiny, image format %d" % fmt)
+    w = config1()
+    ctx = _ctx(w, image_precision=fmt)
+    orc = _oracle(w)
+    ctx.sweep()
+    rep = parity.check_sweep(orc, ctx)
+    _assert_clean(rep, "sweep fmt %d" % fmt)
+    assert rep["n"] == 900
+
+
+@pytest.mark.parametrize("case", ["ragged", "tiny_sp", "large_sp", "two_views", "one_level", "no_jitter",
+                                  "neighbour_subset", "mixed_sizes"])
+def test_sweep_parity_edge_cases(case):
+    _say("sweep edge case %s" % case)
+    if case == "ragged":
+        w = tiny_custom(161, 117, 13, 9, seed=3, levels=24)
+    elif case == "tiny_sp":
+        w = tiny_custom(160, 120, 40, 30, seed=5, levels=16, labels="grid")
+    elif case == "large_sp":
+        w = tiny_custom(160, 120, 2, 2, seed=6, levels=8, labels="grid")
+    elif case == "two_views":
+        w = tiny_custom(96, 72, 8, 6, n_views=2, seed=8, levels=20)
+    elif case == "one_level":
+        w = tiny_custom(96, 72, 8, 6, seed=9, levels=1)
+    elif case == "no_jitter":
+        w = tiny_custom(96, 72, 8, 6, seed=10, levels=20)
+        w.params.jitter = 0
+    elif case == "neighbour_subset":
+        w = tiny_custom(96, 72, 8, 6, n_views=4, seed=11, levels=20)
+        w.rig.neighbors = [[1], [0, 2], [3, 1], [2]]
+    else:
+        w = _mixed_size_workload()
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    ctx.sweep()
+    rep = parity.check_sweep(orc, ctx)
+    _assert_clean(rep, "sweep %s" % case)
+
+
+def _mixed_size_workload():
+    from lfsynth.configs import MethodParams, Workload
+    from lfsynth.rig import View, intrinsics, pose_from_centre
+
+    rng = np.random.Generator(np.random.PCG64(12))
+    views = []
+    for (W, H, f, x) in ((160, 120, 200.0, -0.1), (200, 150, 250.0, 0.0), (128, 96, 160.0, 0.1)):
+        R, t = pose_from_centre([x, 0, 0])
+        views.append(View(W, H, intrinsics(f, W, H), R, t))
+    scene = make_scene(rng, f=200.0, W=160, H=120, sp_px=64.0, n_rect=3)
+    r = build_rig(views[:1], scene, 20, 15)
+    r2 = build_rig(views[1:2], scene, 25, 19)
+    r3 = build_rig(views[2:], scene, 16, 12)
+    r.views = r.views + r2.views + r3.views
+    return Workload("mixed-sizes", r, MethodParams(levels=24, iterations=2))
+
+
+# ------------------------------------------------------------------ a6-a8: refinement (lockstep)
+
+def test_refine_lockstep_tiny():
+    _say("refine lockstep tiny, 3 iterations")
+    _lockstep(config1(), 3)
+
+
+@pytest.mark.parametrize("case", ["ragged", "holes", "two_views", "neighbour_subset", "large_sp"])
+def test_refine_lockstep_edge_cases(case):
+    _say("refine lockstep edge case %s" % case)
+    if case == "ragged":
+        w = tiny_custom(161, 117, 13, 9, seed=3, levels=24)
+    elif case == "holes":
+        w = tiny_custom(96, 64, 8, 6, seed=4, labels="grid", levels=16)
+        for v in w.rig.views:
+            v.labels[v.labels == 9] = 10
+            v.labels[v.labels == 30] = 22
+    elif case == "two_views":
+        w = tiny_custom(96, 72, 8, 6, n_views=2, seed=8, levels=20)
+    elif case == "neighbour_subset":
+        w = tiny_custom(96, 72, 8, 6, n_views=4, seed=11, levels=20)
+        w.rig.neighbors = [[1], [0, 2], [3, 1], [2]]
+    else:
+        w = tiny_custom(160, 120, 4, 3, seed=6, levels=8, labels="grid")
+    _lockstep(w, 2)
+
+
+@pytest.mark.parametrize("mask", [1, 2, 6, 3])
+def test_refine_lockstep_term_ablations(mask):
+    _say("refine lockstep term_mask %d" % mask)
+    w = config1()
+    w.params.term_mask = mask
+    _lockstep(w, 1)
+
+
+def test_refine_lockstep_data_only_mode():
+    _say("refine lockstep data-only energy")
+    w = config1()
+    w.params.energy_mode = 1
+    _lockstep(w, 2)
+
+
+def test_refine_lockstep_random_state():
+    """A given (non-sweep) state with slanted planes exercises every normal and
+    occlusion path."""
+    from lfsynth import random_planes
+
+    _say("refine lockstep random slanted state")
+    w = config1()
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    rng = np.random.default_rng(5)
+    A = np.concatenate([random_planes(rng, v.gw, v.gh, 2.0, 8.0) for v in w.rig.views])
+    A64 = parity.round_state(A)
+    for v in range(orc.V):
+        ctx.set_planes(v, A64[orc.view_slice(v)])
+    ctx.propagate(1, 1)
+    rep = parity.check_refine(orc, ctx, A64, 1)
+    _assert_clean(rep, "random-state refine")
+
+
+# ------------------------------------------------------------------ a9: depth readout
+
+def test_depth_readout_matches_oracle():
+    from lfsynth import random_planes
+
+    _say("depth readout")
+    w = config1()
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    rng = np.random.default_rng(9)
+    A64 = parity.round_state(np.concatenate([random_planes(rng, v.gw, v.gh, 2.0, 8.0) for v in w.rig.views]))
+    for v in range(orc.V):
+        ctx.set_planes(v, A64[orc.view_slice(v)])
+    for v in range(orc.V):
+        D_g = ctx.get_depth(v)
+        D_o = orc.render_depth(A64, v)
+        assert np.all((D_g > 0) == (D_o > 0))
+        assert np.allclose(D_g, D_o, rtol=2e-5, atol=0)
+
+
+def test_depth_readout_to_device_buffer_with_stride():
+    import torch
+
+    _say("depth readout into a strided device tensor")
+    w = config1()
+    ctx = _ctx(w)
+    ctx.sweep()
+    host = ctx.get_depth(1)
+    buf = torch.full((120, 200), -1.0, device="cuda:0")
+    ctx.get_depth(1, out=buf[:, 10:170])
+    ctx.synchronize()
+    got = buf.cpu().numpy()
+    assert np.array_equal(got[:, 10:170], host)
+    assert np.all(got[:, :10] == -1) and np.all(got[:, 170:] == -1)
+
+
+# ------------------------------------------------------------------ end to end
+
+def test_end_to_end_depth_error_tiny():
+    _say("end to end tiny: sweep + 3 iterations, independent runs")
+    w = config1()
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    ctx.sweep()
+    ctx.propagate(1, 3)
+    hist = orc.run(3)
+    errs = []
+    for v in range(orc.V):
+        mare, rel = parity.depth_mare(ctx.get_depth(v), orc.render_depth(hist[-1][0], v))
+        errs.append(mare)
+    _say("end-to-end depth MARE per view: %s" % errs)
+    assert max(errs) <= parity.DEPTH_REL
+
+
+def test_device_inputs_match_host_inputs():
+    import torch
+
+    _say("device-resident inputs")
+    w = config1()
+    ctx_h = _ctx(w)
+    ctx_h.sweep()
+    ctx_h.propagate(1, 2)
+    from paper_1812_06856_amd import slf
+
+    ctx_d = slf.Context(0)
+    vs = w.rig.views
+    ctx_d.set_cameras([(v.W, v.H) for v in vs], [v.K for v in vs], [v.R for v in vs], [v.t for v in vs])
+    ctx_d.set_params(slf.params_from(w.params))
+    for i, v in enumerate(vs):
+        ctx_d.set_image(i, torch.from_numpy(v.rgb).cuda())
+        ctx_d.set_labels(i, torch.from_numpy(v.labels).cuda(), v.gw, v.gh)
+    ctx_d.sweep()
+    ctx_d.propagate(1, 2)
+    for v in range(3):
+        a, b = ctx_h.get_planes(v), ctx_d.get_planes(v)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------------ error paths through the ABI
+
+def test_error_paths():
+    import torch
+    from paper_1812_06856_amd import slf
+
+    _say("error paths")
+    w = config1()
+    vs = w.rig.views
+    ctx = slf.Context(0)
+    with pytest.raises(slf.SlfError) as e:
+        ctx.sweep()
+    assert e.value.status == slf.SLF_ESTATE
+    ctx.set_cameras([(v.W, v.H) for v in vs], [v.K for v in vs], [v.R for v in vs], [v.t for v in vs])
+    with pytest.raises(slf.SlfError) as e:
+        ctx.sweep()
+    assert e.value.status == slf.SLF_ESTATE
+    for i, v in enumerate(vs):
+        ctx.set_image(i, v.rgb)
+    bad = vs[0].labels.copy()
+    bad[3, 4] = 300
+    with pytest.raises(slf.SlfError) as e:
+        ctx.set_labels(0, bad, 20, 15)
+    assert e.value.status == slf.SLF_EINVAL
+    for i, v in enumerate(vs):
+        ctx.set_labels(i, torch.from_numpy(bad if i == 0 else v.labels).cuda(), v.gw, v.gh)
+    with pytest.raises(slf.SlfError) as e:
+        ctx.sweep()
+    assert e.value.status == slf.SLF_EINVAL and "label" in ctx.last_error()
+    ctx.set_labels(0, vs[0].labels, 20, 15)
+    with pytest.raises(slf.SlfError) as e:
+        ctx.propagate(1, 1)
+    assert e.value.status == slf.SLF_ESTATE
+    ctx.sweep()
+    planes = ctx.get_planes(0)[0].copy()
+    planes[5, 1:] = [0, 0, -1]
+    with pytest.raises(slf.SlfError) as e:
+        ctx.set_planes(0, planes)
+    assert e.value.status == slf.SLF_EINVAL
+    with pytest.raises(slf.SlfError) as e:
+        ctx.propagate(0, 1)
+    assert e.value.status == slf.SLF_EINVAL
+    with pytest.raises(slf.SlfError) as e:
+        ctx.set_params(slf.default_params(d_min=3.0, d_max=2.0))
+    assert e.value.status == slf.SLF_EINVAL
+    ctx.propagate(1, 1)
+    ctx.synchronize()

@@ -757,3 +757,28 @@ def test_p5_refinement_recovers_slanted_planes_plausibly():
         within.append(ok / tot)
     assert within[1] >= 0.9
     assert within[1] >= within[0] - 0.02
+
+
+def test_forced_pivot_at_the_argmax_reproduces_the_step():
+    """The tie-resolution test hook: forcing the propagation stage to its own
+    winner reproduces the refinement step exactly; forcing another candidate
+    pivots the normals at that candidate's depth."""
+    w = config1()
+    orc = Oracle(w.rig, w.params)
+    A = orc.sweep()[0]
+    rng = np.random.default_rng(17)
+    for g in rng.choice(orc.S, 20, replace=False):
+        v = int(np.searchsorted(orc.sp_off, g, side="right") - 1)
+        s = int(g - orc.sp_off[v])
+        pl, e, ch, mg = orc.refine_sp(A, 1, v, s)
+        slots, planes, en = orc.refine_trace(A, 1, v, s)
+        prop = slots < 1000
+        win = int(slots[prop][np.argmax(en[prop])])
+        pl2, e2, ch2, sl2, pls2, en2 = orc.refine_pivot(A, 1, v, s, win)
+        assert ch2 == ch and e2 == e and np.array_equal(pl2, pl)
+        other = int(slots[prop][-1])
+        pl3, e3, ch3, sl3, pls3, en3 = orc.refine_pivot(A, 1, v, s, other)
+        d_other = planes[prop][-1][0]
+        for slot, row in zip(sl3, pls3):
+            if slot >= 1000:
+                assert row[0] == pytest.approx(d_other, rel=1e-12)
