@@ -96,7 +96,7 @@ struct slf_ctx {
   float4 *d_colour = nullptr;
   PixEntry *d_px = nullptr;
   float4 *d_planes[2] = {nullptr, nullptr};
-  float4 *d_gtab[2] = {nullptr, nullptr};
+  float4 *d_tab[2] = {nullptr, nullptr};  // per superpixel {colour, inverse-depth row}
   float *d_energy = nullptr, *d_margin = nullptr;
   int *d_choice = nullptr;
   unsigned long long *d_work = nullptr;
@@ -105,6 +105,7 @@ struct slf_ctx {
   int cur = 0;
   std::vector<int> area_h;
   std::vector<double2> cen_h;
+  std::vector<float4> col_h;
   uint64_t host_evals = 0, host_samples = 0;
 
   int fail(int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
@@ -172,7 +173,7 @@ void free_sp(slf_ctx *c) {
   dfree(c->d_px);
   for (int j = 0; j < 2; ++j) {
     dfree(c->d_planes[j]);
-    dfree(c->d_gtab[j]);
+    dfree(c->d_tab[j]);
   }
   dfree(c->d_energy);
   dfree(c->d_margin);
@@ -295,7 +296,7 @@ int alloc_sp(slf_ctx *c) {
   if ((rc = ensure_alloc(c, sizeof(PixEntry) * (size_t)c->total_px, (void **)&c->d_px))) return rc;
   for (int j = 0; j < 2; ++j) {
     if ((rc = ensure_alloc(c, sizeof(float4) * S, (void **)&c->d_planes[j]))) return rc;
-    if ((rc = ensure_alloc(c, sizeof(float4) * S, (void **)&c->d_gtab[j]))) return rc;
+    if ((rc = ensure_alloc(c, 2 * sizeof(float4) * S, (void **)&c->d_tab[j]))) return rc;
   }
   if ((rc = ensure_alloc(c, sizeof(float) * S, (void **)&c->d_energy))) return rc;
   if ((rc = ensure_alloc(c, sizeof(float) * S, (void **)&c->d_margin))) return rc;
@@ -342,6 +343,9 @@ int ensure_setup(slf_ctx *c) {
     HIP_OR_FAIL(c, hipMemcpyAsync(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     c->area_h.resize(c->S);
     c->cen_h.resize(c->S);
+    c->col_h.resize(c->S);
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->col_h.data(), c->d_colour, sizeof(float4) * c->S, hipMemcpyDeviceToHost,
+                                  c->stream));
     HIP_OR_FAIL(c, hipMemcpyAsync(c->area_h.data(), c->d_area, sizeof(int) * c->S, hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipMemcpyAsync(c->cen_h.data(), c->d_centroid_d, sizeof(double2) * c->S, hipMemcpyDeviceToHost,
                                   c->stream));
@@ -600,7 +604,8 @@ int slf_sweep(slf_ctx *c) {
   a.jitter = c->p.jitter;
   a.T255 = c->p.tssd_T * 255.f * 255.f;
   a.planes = c->d_planes[c->cur];
-  a.gtab = c->d_gtab[c->cur];
+  a.colour = c->d_colour;
+  a.tab = c->d_tab[c->cur];
   a.cost = c->d_energy;
   a.choice = c->d_choice;
   a.margin = c->d_margin;
@@ -630,12 +635,13 @@ int slf_set_planes(slf_ctx *c, int view, const float *planes) {
   const ViewDev &d = c->views_h[view];
   const ViewHost &h = c->vh[view];
   const int K = d.gw * d.gh;
-  std::vector<float4> pl(K), gt(K);
+  std::vector<float4> pl(K), tab(2 * (size_t)K);
   for (int s = 0; s < K; ++s) {
     const int g = d.sp_off + s;
+    tab[2 * s] = c->col_h[g];
     if (c->area_h[g] == 0) {
       pl[s] = make_float4(0.f, 0.f, 0.f, 0.f);
-      gt[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+      tab[2 * s + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
       continue;
     }
     const double dd = planes[4 * s], n0 = planes[4 * s + 1], n1 = planes[4 * s + 2], n2 = planes[4 * s + 3];
@@ -651,14 +657,14 @@ int slf_set_planes(slf_ctx *c, int view, const float *planes) {
     if (!(tt > 0)) return c->fail(SLF_EINVAL, "view %d cell %d: plane does not face the camera", view, s);
     const double delta = dd * tt;
     pl[s] = make_float4((float)dd, (float)n0, (float)n1, (float)n2);
-    gt[s] = make_float4((float)((n0 * h.Kinv[0] + n1 * h.Kinv[3] + n2 * h.Kinv[6]) / delta),
-                        (float)((n0 * h.Kinv[1] + n1 * h.Kinv[4] + n2 * h.Kinv[7]) / delta),
-                        (float)((n0 * h.Kinv[2] + n1 * h.Kinv[5] + n2 * h.Kinv[8]) / delta), 0.f);
+    tab[2 * s + 1] = make_float4((float)((n0 * h.Kinv[0] + n1 * h.Kinv[3] + n2 * h.Kinv[6]) / delta),
+                                 (float)((n0 * h.Kinv[1] + n1 * h.Kinv[4] + n2 * h.Kinv[7]) / delta),
+                                 (float)((n0 * h.Kinv[2] + n1 * h.Kinv[5] + n2 * h.Kinv[8]) / delta), 0.f);
   }
   HIP_OR_FAIL(c, hipMemcpyAsync(c->d_planes[c->cur] + d.sp_off, pl.data(), sizeof(float4) * K, hipMemcpyHostToDevice,
                                 c->stream));
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_gtab[c->cur] + d.sp_off, gt.data(), sizeof(float4) * K, hipMemcpyHostToDevice,
-                                c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->d_tab[c->cur] + 2 * (size_t)d.sp_off, tab.data(), 2 * sizeof(float4) * K,
+                                hipMemcpyHostToDevice, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->vh[view].has_planes = true;
   return SLF_OK;
@@ -699,9 +705,9 @@ int slf_propagate(slf_ctx *c, int first_iter, int n_iters) {
   for (int it = first_iter; it < first_iter + n_iters; ++it) {
     a.iter = it;
     a.planesA = c->d_planes[c->cur];
-    a.gtabA = c->d_gtab[c->cur];
+    a.tabA = c->d_tab[c->cur];
     a.planesB = c->d_planes[1 - c->cur];
-    a.gtabB = c->d_gtab[1 - c->cur];
+    a.tabB = c->d_tab[1 - c->cur];
     HIP_OR_FAIL(c, launch_refine(c->p.image_precision, a, c->stream));
     c->cur = 1 - c->cur;
   }
@@ -739,7 +745,7 @@ int slf_get_depth(slf_ctx *c, int view, float *out, int64_t stride, int is_devic
   if (stride < d.W) return c->fail(SLF_EINVAL, "row stride %lld < W", (long long)stride);
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   if (is_device) {
-    HIP_OR_FAIL(c, launch_depth(c->d_views, d, view, c->d_labels, c->d_gtab[c->cur], out, stride, c->stream));
+    HIP_OR_FAIL(c, launch_depth(c->d_views, d, view, c->d_labels, c->d_tab[c->cur], out, stride, c->stream));
     return SLF_OK;
   }
   const int64_t n = (int64_t)d.W * d.H;
@@ -749,7 +755,7 @@ int slf_get_depth(slf_ctx *c, int view, float *out, int64_t stride, int is_devic
     if (rc) return rc;
     c->depth_tmp_n = n;
   }
-  HIP_OR_FAIL(c, launch_depth(c->d_views, d, view, c->d_labels, c->d_gtab[c->cur], c->d_depth_tmp, d.W, c->stream));
+  HIP_OR_FAIL(c, launch_depth(c->d_views, d, view, c->d_labels, c->d_tab[c->cur], c->d_depth_tmp, d.W, c->stream));
   HIP_OR_FAIL(c, hipMemcpy2DAsync(out, sizeof(float) * stride, c->d_depth_tmp, sizeof(float) * d.W,
                                   sizeof(float) * d.W, d.H, hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
@@ -769,17 +775,12 @@ int slf_get_superpixels(slf_ctx *c, int view, int32_t *area, float *centroid, fl
       centroid[2 * s] = (float)c->cen_h[d.sp_off + s].x;
       centroid[2 * s + 1] = (float)c->cen_h[d.sp_off + s].y;
     }
-  if (colour) {
-    std::vector<float4> tmp(K);
-    HIP_OR_FAIL(c, hipMemcpyAsync(tmp.data(), c->d_colour + d.sp_off, sizeof(float4) * K, hipMemcpyDeviceToHost,
-                                  c->stream));
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (colour)
     for (size_t s = 0; s < K; ++s) {
-      colour[3 * s] = tmp[s].x;
-      colour[3 * s + 1] = tmp[s].y;
-      colour[3 * s + 2] = tmp[s].z;
+      colour[3 * s] = c->col_h[d.sp_off + s].x;
+      colour[3 * s + 1] = c->col_h[d.sp_off + s].y;
+      colour[3 * s + 2] = c->col_h[d.sp_off + s].z;
     }
-  }
   return SLF_OK;
 }
 

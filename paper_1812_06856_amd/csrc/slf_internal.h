@@ -59,8 +59,9 @@ struct SweepArgs {
   uint64_t seed;
   int jitter;
   float T255;          // truncation in squared 0..255 units
+  const float4 *colour;  // mean colour per superpixel
   float4 *planes;      // out
-  float4 *gtab;        // out: inverse-depth row (g0, g1, g2, 0) per superpixel
+  float4 *tab;         // out: per superpixel {colour, inverse-depth row (g0, g1, g2, 0)}
   float *cost;         // out
   int *choice;         // out
   float *margin;       // out
@@ -78,9 +79,9 @@ struct RefineArgs {
   const int *labels;      // all views
   const void *quads;      // images (data-only energy mode)
   const float4 *planesA;  // state read
-  const float4 *gtabA;
+  const float4 *tabA;     // per superpixel {colour, inverse-depth row} of state A
   float4 *planesB;        // state written
-  float4 *gtabB;
+  float4 *tabB;
   float *energy;
   int *choice;
   float *margin;
@@ -103,7 +104,7 @@ hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V
 hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st);
 hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st);
 hipError_t launch_depth(const ViewDev *views_d, const ViewDev &vh, int view, const int *labels,
-                        const float4 *gtab, float *out, int64_t stride, hipStream_t st);
+                        const float4 *tab, float *out, int64_t stride, hipStream_t st);
 size_t quad_bytes(int fmt);
 
 }  // namespace slf

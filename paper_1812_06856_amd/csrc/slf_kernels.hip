@@ -36,16 +36,41 @@ __device__ __forceinline__ double level_q(uint64_t seed, int jitter, double qmin
   return qmin + ((double)k + u) * dq;
 }
 
-// Butterfly sums: every lane ends with the bitwise-identical total.
+// Wave reductions in a fixed order (so results do not depend on
+// scheduling): DPP steps inside each row of 16 lanes (xor 1, xor 2, half-row
+// mirror, row mirror), then the four row sums are read out and added.  The
+// whole wave must be active; the result is uniform.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(x)));
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+constexpr int kDppMirror = 0x140;     // row_mirror
+
+__device__ __forceinline__ float rd_f(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
 __device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
+  x += dpp_f<kDppXor1>(x);
+  x += dpp_f<kDppXor2>(x);
+  x += dpp_f<kDppHalfMirror>(x);
+  x += dpp_f<kDppMirror>(x);
+  return (rd_f(x, 0) + rd_f(x, 16)) + (rd_f(x, 32) + rd_f(x, 48));
 }
 __device__ __forceinline__ int wave_sum_i(int x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-  return x;
+  x += dpp_i<kDppXor1>(x);
+  x += dpp_i<kDppXor2>(x);
+  x += dpp_i<kDppHalfMirror>(x);
+  x += dpp_i<kDppMirror>(x);
+  return (__builtin_amdgcn_readlane(x, 0) + __builtin_amdgcn_readlane(x, 16)) +
+         (__builtin_amdgcn_readlane(x, 32) + __builtin_amdgcn_readlane(x, 48));
 }
 __device__ __forceinline__ long long wave_sum_ll(long long x) {
 #pragma unroll
@@ -82,6 +107,8 @@ __device__ __forceinline__ float bcast(float x, int l) {
 // (x0+1,y0+1) so that one aligned load fetches a whole bilinear footprint.
 
 size_t quad_bytes(int fmt) { return fmt == SLF_FMT_F32 ? 64 : fmt == SLF_FMT_F16 ? 32 : 16; }
+template <int FMT>
+constexpr int kQuadBytes = FMT == SLF_FMT_F32 ? 64 : FMT == SLF_FMT_F16 ? 32 : 16;
 
 template <int FMT>
 __device__ __forceinline__ void fetch_quad(const void *base, int64_t idx, float (&t)[12]);
@@ -361,16 +388,16 @@ hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V
 // always in bounds and issued unconditionally.
 template <int FMT>
 __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm1, float Hm1, int Wi, int Hi,
-                                             const void *quads, int64_t qbase, float r0, float g0, float b0,
-                                             float T) {
+                                             const void *quads, float r0, float g0, float b0, float T) {
   const float rw = rcp(w);
   const float xs = x * rw, ys = y * rw;
-  const bool in = (w > 0.f) & (xs >= 0.f) & (xs <= Wm1) & (ys >= 0.f) & (ys <= Hm1);
+  // clamp (NaN maps to 0 under IEEE min/max); the sample is inside iff unclamped
   const float xc = fminf(fmaxf(xs, 0.f), Wm1), yc = fminf(fmaxf(ys, 0.f), Hm1);
-  const int x0 = max(0, min((int)xc, Wi - 2)), y0 = max(0, min((int)yc, Hi - 2));
+  const bool in = (w > 0.f) & (xc == xs) & (yc == ys);
+  const int x0 = min((int)xc, Wi - 2), y0 = min((int)yc, Hi - 2);
   const float fx = xc - (float)x0, fy = yc - (float)y0;
   float t[12];
-  fetch_quad<FMT>(quads, qbase + (int64_t)y0 * (Wi - 1) + x0, t);
+  fetch_quad<FMT>(quads, (int64_t)(y0 * (Wi - 1) + x0), t);
   float b[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -381,6 +408,11 @@ __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm
   const float d0 = r0 - b[0], d1 = g0 - b[1], d2 = b0 - b[2];
   const float ssd = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
   return in ? fminf(ssd, T) : T;
+}
+
+// Address of view i's texels.
+__device__ __forceinline__ const void *quad_base(const void *quads, int fmt_bytes, int64_t quad_off) {
+  return static_cast<const char *>(quads) + quad_off * fmt_bytes;
 }
 
 // ------------------------------------------------------------------ plane sweep (a2-a5)
@@ -402,7 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   if (A == 0) {
     if (lane == 0) {
       a.planes[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-      a.gtab[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      a.tab[2 * g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      a.tab[2 * g + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
       a.cost[g] = 0.f;
       a.choice[g] = -1;
       a.margin[g] = 0.f;
@@ -430,7 +463,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
     float A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, A5 = 0, A6 = 0, A7 = 0, A8 = 0, bx = 0, by = 0, bw = 0;
     float Wm1 = 0, Hm1 = 0;
     int Wi = 2, Hi = 2;
-    int64_t qbase = 0;
+    const void *qbase = a.quads;
     for (int j = lane; j < P; j += kWave) {
       if (iv != cur) {
         const PairDev &pg = a.pairs[vw.pair_off + iv];
@@ -443,7 +476,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
         Hi = vi.H;
         Wm1 = (float)(Wi - 1);
         Hm1 = (float)(Hi - 1);
-        qbase = vi.quad_off;
+        qbase = quad_base(a.quads, kQuadBytes<FMT>, vi.quad_off);
         cur = iv;
       }
       const PixEntry e = a.px[poff + p];
@@ -455,7 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
 #pragma unroll
       for (int kk = 0; kk < KC; ++kk) {
         acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi,
-                                    Hi, a.quads, qbase, r0, g0, b0, a.T255);
+                                    Hi, qbase, r0, g0, b0, a.T255);
       }
       p += kWave;
       while (p >= A) {
@@ -480,7 +513,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   if (lane == 0) {
     const double qb = level_q(a.seed, a.jitter, a.qmin, a.dq, v, s, kbest);
     a.planes[g] = make_float4((float)(1.0 / qb), 0.f, 0.f, 1.f);
-    a.gtab[g] = make_float4(0.f, 0.f, (float)qb, 0.f);
+    a.tab[2 * g] = a.colour[g];
+    a.tab[2 * g + 1] = make_float4(0.f, 0.f, (float)qb, 0.f);
     const float norm = 1.f / ((float)A * (float)N * a.T255);
     a.cost[g] = best * norm;
     a.choice[g] = kbest;
@@ -488,17 +522,28 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   }
 }
 
+#ifndef SLF_LEVEL_CHUNK
+#define SLF_LEVEL_CHUNK 8
+#endif
+constexpr int kLevelChunk = SLF_LEVEL_CHUNK;
+
 hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st) {
   const dim3 grid((a.S + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);
   switch (fmt) {
-    case SLF_FMT_U8: hipLaunchKernelGGL((k_sweep<SLF_FMT_U8, 16>), grid, block, 0, st, a); break;
-    case SLF_FMT_F16: hipLaunchKernelGGL((k_sweep<SLF_FMT_F16, 16>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_sweep<SLF_FMT_F32, 16>), grid, block, 0, st, a); break;
+    case SLF_FMT_U8: hipLaunchKernelGGL((k_sweep<SLF_FMT_U8, kLevelChunk>), grid, block, 0, st, a); break;
+    case SLF_FMT_F16: hipLaunchKernelGGL((k_sweep<SLF_FMT_F16, kLevelChunk>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_sweep<SLF_FMT_F32, kLevelChunk>), grid, block, 0, st, a); break;
   }
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ refinement (a6-a8)
+
+// Neighbour views sampled together per pixel in the refinement energy.
+#ifndef SLF_VIEW_GROUP
+#define SLF_VIEW_GROUP 4
+#endif
+constexpr int kViewGroup = SLF_VIEW_GROUP;
 
 struct Best {
   float E, second;
@@ -512,6 +557,7 @@ struct Best {
 struct SpCtx {
   int g, v, s, A, N, poff;
   int ub, vb;                // centroid rounded to the nearest pixel
+  float invA;                // 1 / |Omega|
   double rsx, rsy, rsz;      // K_r^-1 (c_s, 1)
   float4 Cs;                 // mean colour
   float omega_min;           // min over ring neighbours of omega(C_s, C_j); 1 without neighbours
@@ -555,8 +601,8 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         const float pu = (float)(e.x & 0xffffu), pv = (float)(e.x >> 16);
         acc += tssd_sample<FMT>(fmaf(H[0], pu, fmaf(H[1], pv, H[2])), fmaf(H[3], pu, fmaf(H[4], pv, H[5])),
                                 fmaf(H[6], pu, fmaf(H[7], pv, H[8])), (float)(vi.W - 1), (float)(vi.H - 1), vi.W,
-                                vi.H, a.quads, vi.quad_off, (float)(e.y & 255u), (float)((e.y >> 8) & 255u),
-                                (float)((e.y >> 16) & 255u), a.T255);
+                                vi.H, quad_base(a.quads, kQuadBytes<FMT>, vi.quad_off), (float)(e.y & 255u),
+                                (float)((e.y >> 8) & 255u), (float)((e.y >> 16) & 255u), a.T255);
       }
     }
     return -wave_sum(acc) / ((float)c.A * (float)c.N * a.T255);
@@ -628,64 +674,94 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         awv = (float)H[7];
       }
       const int nv = min(kWave, c.N - base);
-      for (int jv = 0; jv < nv; ++jv) {
-        const float bax = bcast(ax, jv), baxu = bcast(axu, jv), baxv = bcast(axv, jv);
-        const float bay = bcast(ay, jv), bayu = bcast(ayu, jv), bayv = bcast(ayv, jv);
-        const float baw = bcast(aw, jv), bawu = bcast(awu, jv), bawv = bcast(awv, jv);
-        const int bX0 = __builtin_amdgcn_readlane(X0, jv), bY0 = __builtin_amdgcn_readlane(Y0, jv);
-        const PairDev &pg = a.pairs[vw.pair_off + base + jv];
-        const ViewDev &vi = a.views[pg.i];
-        const float Wm1 = (float)(vi.W - 1), Hm1 = (float)(vi.H - 1);
-        const float fX0 = (float)bX0, fY0 = (float)bY0;
-        const int *lab = a.labels + vi.pix_off;
-        const int Ki = vi.gw * vi.gh;
-        float sw = 0.f, gx = 0.f;
-        int nX = 0;
-        bool anyY = false;
+      // Views in groups of kViewGroup: a lane takes one pixel and samples it
+      // in every view of the group, so the group's label and table gathers
+      // are independent and in flight together.
+      for (int jv0 = 0; jv0 < nv; jv0 += kViewGroup) {
+        float cax[kViewGroup], caxu[kViewGroup], caxv[kViewGroup], cay[kViewGroup], cayu[kViewGroup],
+            cayv[kViewGroup], caw[kViewGroup], cawu[kViewGroup], cawv[kViewGroup], fX0[kViewGroup],
+            fY0[kViewGroup], Wm1[kViewGroup], Hm1[kViewGroup];
+        int Wv[kViewGroup], Km1[kViewGroup];
+        const int *lab[kViewGroup];
+        const float4 *tabv[kViewGroup];
+        float sw[kViewGroup], gx[kViewGroup];
+        int nX[kViewGroup];
+        bool anyY[kViewGroup];
+#pragma unroll
+        for (int k = 0; k < kViewGroup; ++k) {
+          const int jv = min(jv0 + k, nv - 1);
+          cax[k] = bcast(ax, jv);
+          caxu[k] = bcast(axu, jv);
+          caxv[k] = bcast(axv, jv);
+          cay[k] = bcast(ay, jv);
+          cayu[k] = bcast(ayu, jv);
+          cayv[k] = bcast(ayv, jv);
+          caw[k] = bcast(aw, jv);
+          cawu[k] = bcast(awu, jv);
+          cawv[k] = bcast(awv, jv);
+          fX0[k] = (float)__builtin_amdgcn_readlane(X0, jv);
+          fY0[k] = (float)__builtin_amdgcn_readlane(Y0, jv);
+          const ViewDev &vi = a.views[a.pairs[vw.pair_off + base + jv].i];
+          Wm1[k] = (float)(vi.W - 1);
+          Hm1[k] = (float)(vi.H - 1);
+          Wv[k] = vi.W;
+          Km1[k] = vi.gw * vi.gh - 1;
+          lab[k] = a.labels + vi.pix_off;
+          tabv[k] = a.tabA + 2 * vi.sp_off;
+          sw[k] = 0.f;
+          gx[k] = 0.f;
+          nX[k] = 0;
+          anyY[k] = false;
+        }
+        const int ng = min(kViewGroup, nv - jv0);
+        // Branch-free samples: indices are clamped so the label and table
+        // loads are always in bounds; predicates decide what is accumulated.
         for (int p = lane; p < c.A; p += kWave) {
           const PixEntry e = a.px[c.poff + p];
           const float du = (float)((int)(e.x & 0xffffu) - c.ub), dv = (float)((int)(e.x >> 16) - c.vb);
           const float iota = fmaf(gu, du, fmaf(gv, dv, i0));  // 1 / D(p)
-          if (!(iota > 0.f)) continue;
-          const float w = fmaf(bawu, du, fmaf(bawv, dv, baw));
-          if (!(w > 0.f)) continue;
-          const float rw = rcp(w);
-          const float dx = fmaf(baxu, du, fmaf(baxv, dv, bax)) * rw;
-          const float dy = fmaf(bayu, du, fmaf(bayv, dv, bay)) * rw;
-          const float z = w * rcp(iota);  // depth of P in camera i
-          const float uf = fX0 + floorf(dx + 0.5f), vf = fY0 + floorf(dy + 0.5f);
-          if (!(uf >= 0.f && uf <= Wm1 && vf >= 0.f && vf <= Hm1)) continue;
-          int l = lab[(int64_t)vf * vi.W + (int64_t)uf];
-          l = min(max(l, 0), Ki - 1);
-          const int gl = vi.sp_off + l;
-          const float4 Cl = a.colour[gl];
-          const float4 gt = a.gtabA[gl];
-          const float dr = c.Cs.x - Cl.x, dg = c.Cs.y - Cl.y, db = c.Cs.z - Cl.z;
-          sw += __expf(-fmaf(db, db, fmaf(dg, dg, dr * dr)) * a.inv2alpha2);
-          const float den = fmaf(gt.x, fX0 + dx, fmaf(gt.y, fY0 + dy, gt.z));
-          if (den > 0.f) {
-            const float Di = rcp(den);
-            if (z <= Di * tol) {
-              ++nX;
-              const float dz = z - Di;
-              gx += __expf(-dz * dz * a.inv2sig2);
-            } else {
-              anyY = true;
-            }
-          } else {
-            ++nX;  // D(p^i) = +inf: visible, zero agreement
+#pragma unroll
+          for (int k = 0; k < kViewGroup; ++k) {
+            if (k >= ng) break;
+            const float w = fmaf(cawu[k], du, fmaf(cawv[k], dv, caw[k]));  // z_i(P) = w / iota
+            const float rw = rcp(w);
+            const float dx = fmaf(caxu[k], du, fmaf(caxv[k], dv, cax[k])) * rw;
+            const float dy = fmaf(cayu[k], du, fmaf(cayv[k], dv, cay[k])) * rw;
+            const float uf = fX0[k] + floorf(dx + 0.5f), vf = fY0[k] + floorf(dy + 0.5f);
+            const float uc = fminf(fmaxf(uf, 0.f), Wm1[k]), vc = fminf(fmaxf(vf, 0.f), Hm1[k]);
+            const bool seen = (iota > 0.f) & (w > 0.f) & (uc == uf) & (vc == vf);
+            const int l = min(max(lab[k][(int)vc * Wv[k] + (int)uc], 0), Km1[k]);
+            const float4 Cl = tabv[k][2 * l];
+            const float4 gt = tabv[k][2 * l + 1];
+            const float dr = c.Cs.x - Cl.x, dg = c.Cs.y - Cl.y, db = c.Cs.z - Cl.z;
+            const float om = __expf(-fmaf(db, db, fmaf(dg, dg, dr * dr)) * a.inv2alpha2);
+            const float den = fmaf(gt.x, fX0[k] + dx, fmaf(gt.y, fY0[k] + dy, gt.z));  // 1 / D(p^i)
+            const bool front = den > 0.f;
+            // z <= D(p^i) (1 + tau)  <=>  w den <= (1 + tau) iota   (iota, den > 0)
+            const float wd = w * den;
+            const bool vis = !front || (wd <= tol * iota);
+            const float dz = (wd - iota) * rcp(iota * den);  // z - D(p^i)
+            const float gk = __expf(-dz * dz * a.inv2sig2);
+            sw[k] += seen ? om : 0.f;
+            nX[k] += (seen & vis) ? 1 : 0;
+            gx[k] += (seen & vis & front) ? gk : 0.f;
+            anyY[k] |= seen & !vis;
           }
         }
-        sw = wave_sum(sw);
-        gx = wave_sum(gx);
-        nX = wave_sum_i(nX);
-        const bool Y = __ballot(anyY) != 0ull;
-        const float Si = sw / (float)c.A;
-        const float Vi = nX > 0 ? Si * gx / (float)nX : 0.f;
-        sum += Vi + (Y ? occ : 0.f);
+#pragma unroll
+        for (int k = 0; k < kViewGroup; ++k) {
+          if (k >= ng) break;
+          const float swt = wave_sum(sw[k]);
+          const float gxt = wave_sum(gx[k]);
+          const int nXt = wave_sum_i(nX[k]);
+          const bool Y = __ballot(anyY[k]) != 0ull;
+          const float Si = swt * c.invA;
+          const float Vi = nXt > 0 ? Si * gxt * rcp((float)nXt) : 0.f;
+          sum += Vi + (Y ? occ : 0.f);
+        }
       }
     }
-    Ec = sum / (float)c.N;
+    Ec = sum * rcp((float)c.N);
   }
   return Ec * Es;
 }
@@ -745,7 +821,8 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
   if (c.A == 0) {
     if (lane == 0) {
       a.planesB[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-      a.gtabB[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      a.tabB[2 * g] = make_float4(0.f, 0.f, 0.f, 0.f);
+      a.tabB[2 * g + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
       a.energy[g] = 0.f;
       a.choice[g] = -1;
       a.margin[g] = 0.f;
@@ -754,6 +831,7 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
   }
   c.N = vw.n_pairs;
   c.poff = a.px_off[g];
+  c.invA = 1.f / (float)c.A;
   const double2 cs = a.centroid_d[g];
   ray_of(vw, cs, c.rsx, c.rsy, c.rsz);
   c.Cs = a.colour[g];
@@ -845,14 +923,16 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
   if (lane == 0) {
     if (b.slot < 0) {  // no valid candidate: keep the current plane
       a.planesB[g] = a.planesA[g];
-      a.gtabB[g] = a.gtabA[g];
+      a.tabB[2 * g] = a.tabA[2 * g];
+      a.tabB[2 * g + 1] = a.tabA[2 * g + 1];
       a.energy[g] = -INFINITY;
       a.choice[g] = -1;
       a.margin[g] = 0.f;
     } else {
       a.planesB[g] = make_float4((float)b.d, (float)b.nx, (float)b.ny, (float)b.nz);
       const double id = 1.0 / b.delta;
-      a.gtabB[g] = make_float4((float)((b.nx * vw.Kinv_d[0] + b.ny * vw.Kinv_d[3] + b.nz * vw.Kinv_d[6]) * id),
+      a.tabB[2 * g] = c.Cs;
+      a.tabB[2 * g + 1] = make_float4((float)((b.nx * vw.Kinv_d[0] + b.ny * vw.Kinv_d[3] + b.nz * vw.Kinv_d[6]) * id),
                                (float)((b.nx * vw.Kinv_d[1] + b.ny * vw.Kinv_d[4] + b.nz * vw.Kinv_d[7]) * id),
                                (float)((b.nx * vw.Kinv_d[2] + b.ny * vw.Kinv_d[5] + b.nz * vw.Kinv_d[8]) * id), 0.f);
       a.energy[g] = b.E;
@@ -876,23 +956,23 @@ hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st) {
 
 // ------------------------------------------------------------------ depth readout (a9)
 // D(p) = 1 / (g_s . p~) for s = label(p), 0 where the plane does not face the camera.
-__global__ __launch_bounds__(256) void k_depth(const int *labels, int W, int H, int K, int sp_off, const float4 *gtab,
+__global__ __launch_bounds__(256) void k_depth(const int *labels, int W, int H, int K, int sp_off, const float4 *tab,
                                                float *out, int64_t stride) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)W * H) return;
   const int x = (int)(idx % W), y = (int)(idx / W);
   int l = labels[idx];
   l = min(max(l, 0), K - 1);
-  const float4 gt = gtab[sp_off + l];
+  const float4 gt = tab[2 * (sp_off + l) + 1];
   const float den = fmaf(gt.x, (float)x, fmaf(gt.y, (float)y, gt.z));
   out[(int64_t)y * stride + x] = den > 0.f ? 1.f / den : 0.f;
 }
 
-hipError_t launch_depth(const ViewDev *, const ViewDev &vh, int, const int *labels, const float4 *gtab, float *out,
+hipError_t launch_depth(const ViewDev *, const ViewDev &vh, int, const int *labels, const float4 *tab, float *out,
                         int64_t stride, hipStream_t st) {
   const int64_t n = (int64_t)vh.W * vh.H;
   hipLaunchKernelGGL(k_depth, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, labels + vh.pix_off, vh.W, vh.H,
-                     vh.gw * vh.gh, vh.sp_off, gtab, out, stride);
+                     vh.gw * vh.gh, vh.sp_off, tab, out, stride);
   return hipGetLastError();
 }
 
