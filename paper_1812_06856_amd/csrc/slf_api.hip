@@ -235,7 +235,7 @@ int build_geometry(slf_ctx *c) {
     if ((int64_t)sp + K > (int64_t)1 << 30) return c->fail(SLF_EUNSUPPORTED, "too many superpixels");
     sp += (int)K;
     px += (int64_t)h.W * h.H;
-    qd += (int64_t)(h.W - 1) * (h.H - 1);
+    qd += (int64_t)h.W * h.H;
     // pairs: A = K_i R_ri K_r^-1, b = K_i t_ri, R_ri = R_i R_r^T, t_ri = t_i - R_ri t_r
     for (int i : h.nbrs) {
       const ViewHost &hi = c->vh[i];
@@ -317,7 +317,7 @@ int ensure_setup(slf_ctx *c) {
   const int fmt = c->p.image_precision;
   if (c->quads_dirty || c->quads_fmt != fmt) {
     int64_t texels = 0;
-    for (const auto &v : c->vh) texels += (int64_t)(v.W - 1) * (v.H - 1);
+    for (const auto &v : c->vh) texels += (int64_t)v.W * v.H;
     const size_t need = (size_t)texels * quad_bytes(fmt);
     if (need > c->quads_bytes) {
       if (c->d_quads) (void)hipFree(c->d_quads);

@@ -103,8 +103,9 @@ __device__ __forceinline__ float bcast(float x, int l) {
 }
 
 // ------------------------------------------------------------------ image texels
-// A texel (x0, y0) holds the four bilinear taps (x0,y0), (x0+1,y0), (x0,y0+1),
-// (x0+1,y0+1) so that one aligned load fetches a whole bilinear footprint.
+// A texel (x0, y0), x0 in [0, W-1], y0 in [0, H-1], holds the four bilinear
+// taps (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1), with the last column and
+// row replicated, so one aligned load fetches a whole bilinear footprint.
 
 size_t quad_bytes(int fmt) { return fmt == SLF_FMT_F32 ? 64 : fmt == SLF_FMT_F16 ? 32 : 16; }
 template <int FMT>
@@ -154,12 +155,12 @@ __device__ __forceinline__ void fetch_quad<SLF_FMT_F32>(const void *base, int64_
 
 __global__ __launch_bounds__(256) void k_quads(const uint8_t *rgb, int W, int H, void *quads, int64_t quad_off,
                                                int fmt) {
-  const int64_t n = (int64_t)(W - 1) * (H - 1);
+  const int64_t n = (int64_t)W * H;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n) return;
-  const int x0 = (int)(idx % (W - 1)), y0 = (int)(idx / (W - 1));
-  const int64_t px[4] = {(int64_t)y0 * W + x0, (int64_t)y0 * W + x0 + 1, (int64_t)(y0 + 1) * W + x0,
-                         (int64_t)(y0 + 1) * W + x0 + 1};
+  const int x0 = (int)(idx % W), y0 = (int)(idx / W);
+  const int x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1);  // replicated edge: weight 0 there
+  const int64_t px[4] = {(int64_t)y0 * W + x0, (int64_t)y0 * W + x1, (int64_t)y1 * W + x0, (int64_t)y1 * W + x1};
   if (fmt == SLF_FMT_U8) {
     uint32_t w[4];
     for (int j = 0; j < 4; ++j) {
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(256) void k_quads(const uint8_t *rgb, int W, int H,
 
 hipError_t launch_quads(int fmt, const uint8_t *rgb, int64_t, int W, int H, void *quads, int64_t quad_off,
                         hipStream_t st) {
-  const int64_t n = (int64_t)(W - 1) * (H - 1);
+  const int64_t n = (int64_t)W * H;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_quads, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rgb, W, H, quads, quad_off, fmt);
   return hipGetLastError();
@@ -391,13 +392,16 @@ __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm
                                              const void *quads, float r0, float g0, float b0, float T) {
   const float rw = rcp(w);
   const float xs = x * rw, ys = y * rw;
-  // clamp (NaN maps to 0 under IEEE min/max); the sample is inside iff unclamped
-  const float xc = fminf(fmaxf(xs, 0.f), Wm1), yc = fminf(fmaxf(ys, 0.f), Hm1);
+  // Clamp into the image; the sample counts only if unclamped (a NaN fails
+  // the equality, and converts to texel 0, so the load stays in bounds).
+  const float xc = __builtin_amdgcn_fmed3f(xs, 0.f, Wm1), yc = __builtin_amdgcn_fmed3f(ys, 0.f, Hm1);
   const bool in = (w > 0.f) & (xc == xs) & (yc == ys);
-  const int x0 = min((int)xc, Wi - 2), y0 = min((int)yc, Hi - 2);
-  const float fx = xc - (float)x0, fy = yc - (float)y0;
+  // Taps at floor(x) and floor(x)+1 with weight fract(x); at x = W-1 the
+  // replicated column has weight 0, which equals clamping the left tap to W-2.
+  const int x0 = (int)xc, y0 = (int)yc;
+  const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
   float t[12];
-  fetch_quad<FMT>(quads, (int64_t)(y0 * (Wi - 1) + x0), t);
+  fetch_quad<FMT>(quads, (int64_t)(y0 * Wi + x0), t);
   float b[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -425,7 +429,7 @@ __device__ __forceinline__ const void *quad_base(const void *quads, int fmt_byte
 template <int FMT, int KC>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int g = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
   if (g >= a.S) return;
   const int v = a.sp_view[g];
   const ViewDev &vw = a.views[v];
@@ -539,9 +543,14 @@ hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st) {
 
 // ------------------------------------------------------------------ refinement (a6-a8)
 
+#ifndef SLF_XCD_REMAP
+#define SLF_XCD_REMAP 1
+#endif
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+
 // Neighbour views sampled together per pixel in the refinement energy.
 #ifndef SLF_VIEW_GROUP
-#define SLF_VIEW_GROUP 4
+#define SLF_VIEW_GROUP 1
 #endif
 constexpr int kViewGroup = SLF_VIEW_GROUP;
 
@@ -766,52 +775,107 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
   return Ec * Es;
 }
 
-template <int FMT>
-__device__ __forceinline__ void consider(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, Best &b, double nx,
-                                         double ny, double nz, double delta, int slot) {
-  const double tt = nx * c.rsx + ny * c.rsy + nz * c.rsz;
-  if (!(tt > 0.0) || !(delta > 0.0)) return;  // not in front of camera r at this centroid
-  const float E = energy<FMT>(a, c, vw, nx, ny, nz, delta);
-  ++b.evaluated;
-  if (b.slot < 0 || E > b.E) {
-    if (b.slot >= 0) b.second = b.E;
-    b.E = E;
-    b.slot = slot;
-    b.d = delta / tt;
-    b.nx = nx;
-    b.ny = ny;
-    b.nz = nz;
-    b.delta = delta;
-  } else if (E > b.second) {
-    b.second = E;
-  }
-}
-
 __device__ __forceinline__ void ray_of(const ViewDev &vw, double2 cp, double &x, double &y, double &z) {
   x = vw.Kinv_d[0] * cp.x + vw.Kinv_d[1] * cp.y + vw.Kinv_d[2];
   y = vw.Kinv_d[3] * cp.x + vw.Kinv_d[4] * cp.y + vw.Kinv_d[5];
   z = vw.Kinv_d[6] * cp.x + vw.Kinv_d[7] * cp.y + vw.Kinv_d[8];
 }
 
-// Candidate from the stored plane of cell k of the same view (same 3D plane).
+// One candidate plane n . X = delta of camera r, its depth d at the
+// superpixel's centroid and its slot number.
+struct Cand {
+  double nx, ny, nz, delta, d;
+  int slot, pad;
+};
+constexpr int kCandBatch = kWave;  // candidates generated per batch (one per lane)
+
+// Wave-uniform copies (the value of the first active lane, held in SGPRs).
+__device__ __forceinline__ double uni_d(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Makes earlier LDS writes of any lane of this wave visible to its later reads.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Appends this lane's candidate (if valid) to list[base..] keeping lane
+// order; returns the number appended (uniform).
+__device__ __forceinline__ int append_cand(Cand *list, int base, bool valid, const Cand &cd) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t mask = __ballot(valid);
+  if (valid) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = cd;
+  return __popcll(mask);
+}
+
+// Evaluates list[0..n) in order; a candidate replaces the best only on a
+// strictly larger energy (Sec. III-C), so ties keep the earlier slot.
 template <int FMT>
-__device__ __forceinline__ void consider_cell(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, Best &b,
-                                              int k, int slot) {
-  const int gk = vw.sp_off + k;
-  const float4 pk = a.planesA[gk];
-  double rx, ry, rz;
-  ray_of(vw, a.centroid_d[gk], rx, ry, rz);
-  const double nx = pk.y, ny = pk.z, nz = pk.w;
-  consider<FMT>(a, c, vw, b, nx, ny, nz, (double)pk.x * (nx * rx + ny * ry + nz * rz), slot);
+__device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, const Cand *list, int n, Best &b) {
+  for (int k = 0; k < n; ++k) {
+    Cand cd = list[k];
+    cd.nx = uni_d(cd.nx);
+    cd.ny = uni_d(cd.ny);
+    cd.nz = uni_d(cd.nz);
+    cd.delta = uni_d(cd.delta);
+    cd.d = uni_d(cd.d);
+    cd.slot = __builtin_amdgcn_readfirstlane(cd.slot);
+    const float E = energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta);
+    ++b.evaluated;
+    if (b.slot < 0 || E > b.E) {
+      if (b.slot >= 0) b.second = b.E;
+      b.E = E;
+      b.slot = cd.slot;
+      b.d = cd.d;
+      b.nx = cd.nx;
+      b.ny = cd.ny;
+      b.nz = cd.nz;
+      b.delta = cd.delta;
+    } else if (E > b.second) {
+      b.second = E;
+    }
+  }
+}
+
+// Block index with XCD-aware placement: the hardware hands block b to XCD
+// b mod 8, so logical block (b mod 8) * per + b / 8 gives each XCD one
+// contiguous range of superpixels (in raster order within a view), keeping
+// its gathers inside that XCD's L2.  Returns -1 for padding blocks.
+__device__ __forceinline__ int logical_block(int nblocks) {
+#if SLF_XCD_REMAP
+  const int per = (nblocks + kXcds - 1) / kXcds;
+  const int l = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  return l < nblocks ? l : -1;
+#else
+  return (int)blockIdx.x < nblocks ? (int)blockIdx.x : -1;
+#endif
+}
+__host__ __device__ inline int launch_blocks(int nblocks) {
+#if SLF_XCD_REMAP
+  return ((nblocks + kXcds - 1) / kXcds) * kXcds;
+#else
+  return nblocks;
+#endif
 }
 
 // One refinement step per superpixel (Sec. III-C): propagation over the
 // kernel, then 8 triangle normals pivoting at the winner's centroid depth.
+// Candidates are generated lane-parallel in slot order into an LDS list and
+// evaluated in that order by one energy loop.
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
+  __shared__ Cand s_list[kWavesPerBlock][kCandBatch];
   const int lane = threadIdx.x & (kWave - 1);
-  const int g = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int wid = threadIdx.x >> 6;
+  const int blk = logical_block((a.S + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (blk < 0) return;
+  const int g = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + wid);
   if (g >= a.S) return;
+  Cand *list = s_list[wid];
   SpCtx c;
   c.g = g;
   c.v = a.sp_view[g];
@@ -872,52 +936,95 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
   b.evaluated = 0;
   b.d = b.nx = b.ny = b.nz = b.delta = 0.0;
 
-  // propagation: current plane, ring, far star
-  consider_cell<FMT>(a, c, vw, b, c.s, 0);
-  for (int j = 0; j < 8; ++j) {
-    const int k = __builtin_amdgcn_readlane(c.ring_cell, j);
-    if (k >= 0) consider_cell<FMT>(a, c, vw, b, k, 1 + j);
-  }
+  // Propagation (Sec. III-C, eq. 4): slot r = 0 the current plane, 1 + j ring
+  // neighbour j, 9 + 8 (m / step - 1) + j the cell m cells away along ring
+  // direction j, m = step, 2 step, ... <= floor(R_init / I).  A candidate is
+  // the neighbour's 3D plane; it is skipped when its cell is outside the
+  // grid or empty, or when the plane does not face camera r at this centroid.
   const int R = vw.kr_init / a.iter;
-  for (int m = a.kernel_step; m <= R; m += a.kernel_step) {
-    for (int j = 0; j < 8; ++j) {
-      const int x = gx + m * kRingDx[j], y = gy + m * kRingDy[j];
-      if (x < 0 || x >= vw.gw || y < 0 || y >= vw.gh) continue;
-      const int k = y * vw.gw + x;
-      if (a.area[vw.sp_off + k] <= 0) continue;
-      consider_cell<FMT>(a, c, vw, b, k, 9 + 8 * (m / a.kernel_step - 1) + j);
+  const int n_raw = 9 + 8 * (R / a.kernel_step);
+  for (int r0 = 0; r0 < n_raw; r0 += kCandBatch) {
+    const int r = r0 + lane;
+    bool valid = false;
+    Cand cd;
+    cd.slot = r;
+    cd.pad = 0;
+    if (r < n_raw) {
+      int x = gx, y = gy;
+      if (r >= 1 && r <= 8) {
+        x += kRingDx[r - 1];
+        y += kRingDy[r - 1];
+      } else if (r >= 9) {
+        const int m = a.kernel_step * ((r - 9) / 8 + 1), j = (r - 9) % 8;
+        x += m * kRingDx[j];
+        y += m * kRingDy[j];
+      }
+      if (x >= 0 && x < vw.gw && y >= 0 && y < vw.gh) {
+        const int gk = vw.sp_off + y * vw.gw + x;
+        if (a.area[gk] > 0) {
+          const float4 pk = a.planesA[gk];
+          double rx, ry, rz;
+          ray_of(vw, a.centroid_d[gk], rx, ry, rz);
+          cd.nx = pk.y;
+          cd.ny = pk.z;
+          cd.nz = pk.w;
+          cd.delta = (double)pk.x * (cd.nx * rx + cd.ny * ry + cd.nz * rz);
+          const double tt = cd.nx * c.rsx + cd.ny * c.rsy + cd.nz * c.rsz;
+          valid = tt > 0.0 && cd.delta > 0.0;
+          cd.d = cd.delta / tt;
+        }
+      }
     }
+    const int n = append_cand(list, 0, valid, cd);
+    wave_lds_sync();
+    evaluate<FMT>(a, c, vw, list, n, b);
+    wave_lds_sync();
   }
 
-  // triangle normals (Sec. III-C): plane through X_s (winner's depth) and the
-  // 3D centroids of ring neighbours j, j+1 at their depths in A, in FP64
+  // Triangle normals (Sec. III-C): lane j < 8 forms the plane through X_s
+  // (the winner's centroid depth) and the 3D centroids of ring neighbours j
+  // and j+1 at their depths in the state, in FP64.
   if (b.slot >= 0) {
-    const double Xs0 = b.d * c.rsx, Xs1 = b.d * c.rsy, Xs2 = b.d * c.rsz;
-    for (int j = 0; j < 8; ++j) {
-      const int j2 = (j + 1) & 7;
-      const int ka = __builtin_amdgcn_readlane(c.ring_cell, j), kb = __builtin_amdgcn_readlane(c.ring_cell, j2);
-      if (ka < 0 || kb < 0) continue;
-      const double da = bcast_d(c.ring_d, j), dbb = bcast_d(c.ring_d, j2);
-      const double ea0 = da * bcast_d(c.rrx, j) - Xs0, ea1 = da * bcast_d(c.rry, j) - Xs1,
-                   ea2 = da * bcast_d(c.rrz, j) - Xs2;
-      const double eb0 = dbb * bcast_d(c.rrx, j2) - Xs0, eb1 = dbb * bcast_d(c.rry, j2) - Xs1,
-                   eb2 = dbb * bcast_d(c.rrz, j2) - Xs2;
+    const int j2 = (lane + 1) & 7;
+    const int kb = __shfl(c.ring_cell, j2, kWave);
+    const double dbb = __shfl(c.ring_d, j2, kWave);
+    const double rbx = __shfl(c.rrx, j2, kWave), rby = __shfl(c.rry, j2, kWave), rbz = __shfl(c.rrz, j2, kWave);
+    bool valid = false;
+    Cand cd;
+    cd.slot = 1000 + lane;
+    cd.pad = 0;
+    cd.nx = cd.ny = cd.nz = cd.delta = cd.d = 0.0;
+    if (lane < 8 && c.ring_cell >= 0 && kb >= 0) {
+      const double Xs0 = b.d * c.rsx, Xs1 = b.d * c.rsy, Xs2 = b.d * c.rsz;
+      const double ea0 = c.ring_d * c.rrx - Xs0, ea1 = c.ring_d * c.rry - Xs1, ea2 = c.ring_d * c.rrz - Xs2;
+      const double eb0 = dbb * rbx - Xs0, eb1 = dbb * rby - Xs1, eb2 = dbb * rbz - Xs2;
       double n0 = ea1 * eb2 - ea2 * eb1;
       double n1 = ea2 * eb0 - ea0 * eb2;
       double n2 = ea0 * eb1 - ea1 * eb0;
       const double len = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
       const double la = sqrt(ea0 * ea0 + ea1 * ea1 + ea2 * ea2), lb = sqrt(eb0 * eb0 + eb1 * eb1 + eb2 * eb2);
-      if (!(len > 1e-12 * la * lb)) continue;
-      n0 /= len;
-      n1 /= len;
-      n2 /= len;
-      if (n0 * c.rsx + n1 * c.rsy + n2 * c.rsz < 0.0) {
-        n0 = -n0;
-        n1 = -n1;
-        n2 = -n2;
+      if (len > 1e-12 * la * lb) {
+        n0 /= len;
+        n1 /= len;
+        n2 /= len;
+        double tt = n0 * c.rsx + n1 * c.rsy + n2 * c.rsz;
+        if (tt < 0.0) {
+          n0 = -n0;
+          n1 = -n1;
+          n2 = -n2;
+          tt = -tt;
+        }
+        cd.nx = n0;
+        cd.ny = n1;
+        cd.nz = n2;
+        cd.delta = n0 * Xs0 + n1 * Xs1 + n2 * Xs2;
+        valid = tt > 0.0 && cd.delta > 0.0;
+        cd.d = cd.delta / tt;
       }
-      consider<FMT>(a, c, vw, b, n0, n1, n2, n0 * Xs0 + n1 * Xs1 + n2 * Xs2, 1000 + j);
     }
+    const int n = append_cand(list, 0, valid, cd);
+    wave_lds_sync();
+    evaluate<FMT>(a, c, vw, list, n, b);
   }
 
   if (lane == 0) {
@@ -933,8 +1040,9 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
       const double id = 1.0 / b.delta;
       a.tabB[2 * g] = c.Cs;
       a.tabB[2 * g + 1] = make_float4((float)((b.nx * vw.Kinv_d[0] + b.ny * vw.Kinv_d[3] + b.nz * vw.Kinv_d[6]) * id),
-                               (float)((b.nx * vw.Kinv_d[1] + b.ny * vw.Kinv_d[4] + b.nz * vw.Kinv_d[7]) * id),
-                               (float)((b.nx * vw.Kinv_d[2] + b.ny * vw.Kinv_d[5] + b.nz * vw.Kinv_d[8]) * id), 0.f);
+                                      (float)((b.nx * vw.Kinv_d[1] + b.ny * vw.Kinv_d[4] + b.nz * vw.Kinv_d[7]) * id),
+                                      (float)((b.nx * vw.Kinv_d[2] + b.ny * vw.Kinv_d[5] + b.nz * vw.Kinv_d[8]) * id),
+                                      0.f);
       a.energy[g] = b.E;
       a.choice[g] = b.slot;
       a.margin[g] = b.evaluated > 1 ? b.E - b.second : INFINITY;
@@ -945,7 +1053,7 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
 }
 
 hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st) {
-  const dim3 grid((a.S + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);
+  const dim3 grid(launch_blocks((a.S + kWavesPerBlock - 1) / kWavesPerBlock)), block(kBlock);
   switch (fmt) {
     case SLF_FMT_U8: hipLaunchKernelGGL((k_refine<SLF_FMT_U8>), grid, block, 0, st, a); break;
     case SLF_FMT_F16: hipLaunchKernelGGL((k_refine<SLF_FMT_F16>), grid, block, 0, st, a); break;
