@@ -699,6 +699,8 @@ int slf_propagate(slf_ctx *c, int first_iter, int n_iters) {
   a.term_mask = c->p.term_mask;
   a.inv2sig2 = 1.f / (2.f * c->p.sigma * c->p.sigma);
   a.inv2alpha2 = 1.f / (2.f * c->p.alpha * c->p.alpha);
+  a.inv2sig2_log2e = (float)(1.4426950408889634 / (2.0 * (double)c->p.sigma * (double)c->p.sigma));
+  a.inv2alpha2_log2e = (float)(1.4426950408889634 / (2.0 * (double)c->p.alpha * (double)c->p.alpha));
   a.eta = c->p.eta;
   a.occ_tol = c->p.occ_tol;
   a.T255 = c->p.tssd_T * 255.f * 255.f;

@@ -92,6 +92,7 @@ struct RefineArgs {
   int energy_mode;
   unsigned term_mask;
   float inv2sig2, inv2alpha2, eta, occ_tol, T255;
+  float inv2sig2_log2e, inv2alpha2_log2e;  // the same scales times log2(e), for exp2
 };
 
 // Host-side launchers (slf_kernels.hip).

@@ -419,6 +419,32 @@ __device__ __forceinline__ const void *quad_base(const void *quads, int fmt_byte
   return static_cast<const char *>(quads) + quad_off * fmt_bytes;
 }
 
+#ifndef SLF_XCD_REMAP
+#define SLF_XCD_REMAP 1
+#endif
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+
+// Block index with XCD-aware placement: the hardware hands block b to XCD
+// b mod 8, so logical block (b mod 8) * per + b / 8 gives each XCD one
+// contiguous range of superpixels (in raster order within a view), keeping
+// its gathers inside that XCD's L2.  Returns -1 for padding blocks.
+__device__ __forceinline__ int logical_block(int nblocks) {
+#if SLF_XCD_REMAP
+  const int per = (nblocks + kXcds - 1) / kXcds;
+  const int l = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  return l < nblocks ? l : -1;
+#else
+  return (int)blockIdx.x < nblocks ? (int)blockIdx.x : -1;
+#endif
+}
+__host__ __device__ inline int launch_blocks(int nblocks) {
+#if SLF_XCD_REMAP
+  return ((nblocks + kXcds - 1) / kXcds) * kXcds;
+#else
+  return nblocks;
+#endif
+}
+
 // ------------------------------------------------------------------ plane sweep (a2-a5)
 // Level-chunked: each lane takes (neighbour view, pixel) pairs of the
 // superpixel; for a pair, a = A p~ is formed once and the KC levels of the
@@ -429,7 +455,9 @@ __device__ __forceinline__ const void *quad_base(const void *quads, int fmt_byte
 template <int FMT, int KC>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+  const int blk = logical_block((a.S + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (blk < 0) return;
+  const int g = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + (threadIdx.x >> 6));
   if (g >= a.S) return;
   const int v = a.sp_view[g];
   const ViewDev &vw = a.views[v];
@@ -532,7 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
 constexpr int kLevelChunk = SLF_LEVEL_CHUNK;
 
 hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st) {
-  const dim3 grid((a.S + kWavesPerBlock - 1) / kWavesPerBlock), block(kBlock);
+  const dim3 grid(launch_blocks((a.S + kWavesPerBlock - 1) / kWavesPerBlock)), block(kBlock);
   switch (fmt) {
     case SLF_FMT_U8: hipLaunchKernelGGL((k_sweep<SLF_FMT_U8, kLevelChunk>), grid, block, 0, st, a); break;
     case SLF_FMT_F16: hipLaunchKernelGGL((k_sweep<SLF_FMT_F16, kLevelChunk>), grid, block, 0, st, a); break;
@@ -543,10 +571,8 @@ hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st) {
 
 // ------------------------------------------------------------------ refinement (a6-a8)
 
-#ifndef SLF_XCD_REMAP
-#define SLF_XCD_REMAP 1
-#endif
-constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+
+constexpr int kLdsPix = 1024;  // pixels of a superpixel staged in LDS (the rest read from the list)
 
 // Neighbour views sampled together per pixel in the refinement energy.
 #ifndef SLF_VIEW_GROUP
@@ -567,6 +593,7 @@ struct SpCtx {
   int g, v, s, A, N, poff;
   int ub, vb;                // centroid rounded to the nearest pixel
   float invA;                // 1 / |Omega|
+  const uint32_t *pix_lds;   // the first kLdsPix pixels (u | v << 16), staged in LDS
   double rsx, rsy, rsz;      // K_r^-1 (c_s, 1)
   float4 Cs;                 // mean colour
   float omega_min;           // min over ring neighbours of omega(C_s, C_j); 1 without neighbours
@@ -726,8 +753,8 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         // Branch-free samples: indices are clamped so the label and table
         // loads are always in bounds; predicates decide what is accumulated.
         for (int p = lane; p < c.A; p += kWave) {
-          const PixEntry e = a.px[c.poff + p];
-          const float du = (float)((int)(e.x & 0xffffu) - c.ub), dv = (float)((int)(e.x >> 16) - c.vb);
+          const uint32_t uv = p < kLdsPix ? c.pix_lds[p] : a.px[c.poff + p].x;
+          const float du = (float)((int)(uv & 0xffffu) - c.ub), dv = (float)((int)(uv >> 16) - c.vb);
           const float iota = fmaf(gu, du, fmaf(gv, dv, i0));  // 1 / D(p)
 #pragma unroll
           for (int k = 0; k < kViewGroup; ++k) {
@@ -737,20 +764,22 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
             const float dx = fmaf(caxu[k], du, fmaf(caxv[k], dv, cax[k])) * rw;
             const float dy = fmaf(cayu[k], du, fmaf(cayv[k], dv, cay[k])) * rw;
             const float uf = fX0[k] + floorf(dx + 0.5f), vf = fY0[k] + floorf(dy + 0.5f);
-            const float uc = fminf(fmaxf(uf, 0.f), Wm1[k]), vc = fminf(fmaxf(vf, 0.f), Hm1[k]);
+            // clamp into the image (a NaN fails the equality and converts to 0)
+            const float uc = __builtin_amdgcn_fmed3f(uf, 0.f, Wm1[k]), vc = __builtin_amdgcn_fmed3f(vf, 0.f, Hm1[k]);
             const bool seen = (iota > 0.f) & (w > 0.f) & (uc == uf) & (vc == vf);
-            const int l = min(max(lab[k][(int)vc * Wv[k] + (int)uc], 0), Km1[k]);
-            const float4 Cl = tabv[k][2 * l];
-            const float4 gt = tabv[k][2 * l + 1];
+            const uint32_t pix = (uint32_t)(int)vc * (uint32_t)Wv[k] + (uint32_t)(int)uc;
+            const uint32_t l = (uint32_t)min(max(lab[k][pix], 0), Km1[k]);
+            const float4 Cl = tabv[k][2u * l];
+            const float4 gt = tabv[k][2u * l + 1u];
             const float dr = c.Cs.x - Cl.x, dg = c.Cs.y - Cl.y, db = c.Cs.z - Cl.z;
-            const float om = __expf(-fmaf(db, db, fmaf(dg, dg, dr * dr)) * a.inv2alpha2);
+            const float om = __builtin_amdgcn_exp2f(-fmaf(db, db, fmaf(dg, dg, dr * dr)) * a.inv2alpha2_log2e);
             const float den = fmaf(gt.x, fX0[k] + dx, fmaf(gt.y, fY0[k] + dy, gt.z));  // 1 / D(p^i)
             const bool front = den > 0.f;
             // z <= D(p^i) (1 + tau)  <=>  w den <= (1 + tau) iota   (iota, den > 0)
             const float wd = w * den;
             const bool vis = !front || (wd <= tol * iota);
             const float dz = (wd - iota) * rcp(iota * den);  // z - D(p^i)
-            const float gk = __expf(-dz * dz * a.inv2sig2);
+            const float gk = __builtin_amdgcn_exp2f(-dz * dz * a.inv2sig2_log2e);
             sw[k] += seen ? om : 0.f;
             nX[k] += (seen & vis) ? 1 : 0;
             gx[k] += (seen & vis & front) ? gk : 0.f;
@@ -841,27 +870,6 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
   }
 }
 
-// Block index with XCD-aware placement: the hardware hands block b to XCD
-// b mod 8, so logical block (b mod 8) * per + b / 8 gives each XCD one
-// contiguous range of superpixels (in raster order within a view), keeping
-// its gathers inside that XCD's L2.  Returns -1 for padding blocks.
-__device__ __forceinline__ int logical_block(int nblocks) {
-#if SLF_XCD_REMAP
-  const int per = (nblocks + kXcds - 1) / kXcds;
-  const int l = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
-  return l < nblocks ? l : -1;
-#else
-  return (int)blockIdx.x < nblocks ? (int)blockIdx.x : -1;
-#endif
-}
-__host__ __device__ inline int launch_blocks(int nblocks) {
-#if SLF_XCD_REMAP
-  return ((nblocks + kXcds - 1) / kXcds) * kXcds;
-#else
-  return nblocks;
-#endif
-}
-
 // One refinement step per superpixel (Sec. III-C): propagation over the
 // kernel, then 8 triangle normals pivoting at the winner's centroid depth.
 // Candidates are generated lane-parallel in slot order into an LDS list and
@@ -869,6 +877,7 @@ __host__ __device__ inline int launch_blocks(int nblocks) {
 template <int FMT>
 __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
   __shared__ Cand s_list[kWavesPerBlock][kCandBatch];
+  __shared__ uint32_t s_pix[kWavesPerBlock][kLdsPix];
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x >> 6;
   const int blk = logical_block((a.S + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -896,6 +905,9 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
   c.N = vw.n_pairs;
   c.poff = a.px_off[g];
   c.invA = 1.f / (float)c.A;
+  for (int p = lane; p < min(c.A, kLdsPix); p += kWave) s_pix[wid][p] = a.px[c.poff + p].x;
+  c.pix_lds = s_pix[wid];
+  wave_lds_sync();
   const double2 cs = a.centroid_d[g];
   ray_of(vw, cs, c.rsx, c.rsy, c.rsz);
   c.Cs = a.colour[g];
