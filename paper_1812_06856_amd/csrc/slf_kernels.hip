@@ -402,15 +402,51 @@ __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm
   const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
   float t[12];
   fetch_quad<FMT>(quads, (int64_t)(y0 * Wi + x0), t);
+  // bilinear weights of the four taps (FP16 taps feed mixed-precision FMAs directly)
+  const float ofx = 1.f - fx, ofy = 1.f - fy;
+  const float w00 = ofx * ofy, w10 = fx * ofy, w01 = ofx * fy, w11 = fx * fy;
   float b[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const float top = fmaf(fx, t[3 + c] - t[c], t[c]);
-    const float bot = fmaf(fx, t[9 + c] - t[6 + c], t[6 + c]);
-    b[c] = fmaf(fy, bot - top, top);
-  }
+  for (int c = 0; c < 3; ++c) b[c] = fmaf(w11, t[9 + c], fmaf(w01, t[6 + c], fmaf(w10, t[3 + c], w00 * t[c])));
   const float d0 = r0 - b[0], d1 = g0 - b[1], d2 = b0 - b[2];
   const float ssd = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+  return in ? fminf(ssd, T) : T;
+}
+
+// Precision form: FP16 texels interpolated with packed FP16 FMAs (two
+// channels per instruction), the squared difference summed by a dot
+// product with FP32 accumulation, the cost accumulated in FP32.  Taps are
+// exact in FP16 (integers 0..255); the interpolated colour carries FP16
+// rounding (<= 0.125 grey levels).
+template <>
+__device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, float w, float Wm1, float Hm1, int Wi,
+                                                          int Hi, const void *quads, float r0, float g0, float b0,
+                                                          float T) {
+  const float rw = rcp(w);
+  const float xs = x * rw, ys = y * rw;
+  const float xc = __builtin_amdgcn_fmed3f(xs, 0.f, Wm1), yc = __builtin_amdgcn_fmed3f(ys, 0.f, Hm1);
+  const bool in = (w > 0.f) & (xc == xs) & (yc == ys);
+  const int x0 = (int)xc, y0 = (int)yc;
+  const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
+  const uint4 *q = static_cast<const uint4 *>(quads) + 2 * (int64_t)(y0 * Wi + x0);
+  const uint4 lo = q[0], hi = q[1];
+  const float ofx = 1.f - fx, ofy = 1.f - fy;
+  const __half2 w00 = __float2half2_rn(ofx * ofy), w10 = __float2half2_rn(fx * ofy);
+  const __half2 w01 = __float2half2_rn(ofx * fy), w11 = __float2half2_rn(fx * fy);
+  auto h2 = [](uint32_t u) { return *reinterpret_cast<const __half2 *>(&u); };
+  __half2 rg = __hmul2(w00, h2(lo.x));
+  rg = __hfma2(w10, h2(lo.z), rg);
+  rg = __hfma2(w01, h2(hi.x), rg);
+  rg = __hfma2(w11, h2(hi.z), rg);
+  __half2 bz = __hmul2(w00, h2(lo.y));
+  bz = __hfma2(w10, h2(lo.w), bz);
+  bz = __hfma2(w01, h2(hi.y), bz);
+  bz = __hfma2(w11, h2(hi.w), bz);
+  const __half2 drg = __hsub2(__floats2half2_rn(r0, g0), rg);
+  const __half2 db = __hsub2(__floats2half2_rn(b0, 0.f), bz);
+  typedef _Float16 hv2 __attribute__((ext_vector_type(2)));
+  const hv2 vrg = *reinterpret_cast<const hv2 *>(&drg), vb = *reinterpret_cast<const hv2 *>(&db);
+  const float ssd = __builtin_amdgcn_fdot2(vrg, vrg, __builtin_amdgcn_fdot2(vb, vb, 0.f, false), false);
   return in ? fminf(ssd, T) : T;
 }
 

@@ -27,10 +27,11 @@ def gpu_state(ctx, n_views):
     return [np.concatenate([o[i] for o in out]) for i in range(4)]
 
 
-def check_sweep(orc, ctx, sample=None):
+def check_sweep(orc, ctx, sample=None, margin=MARGIN, rel=REL, abs_=ABS):
     """Compares the GPU's sweep output with the oracle's per superpixel.
 
-    sample: None (all superpixels) or an iterable of (view, sp).  Returns a report dict.
+    sample: None (all superpixels) or an iterable of (view, sp); margin and
+    rel default to the FP32 path's bar.  Returns a report dict.
     """
     P_g, C_g, K_g, M_g = gpu_state(ctx, orc.V)
     area = orc.sp_stats()[0]
@@ -51,20 +52,20 @@ def check_sweep(orc, ctx, sample=None):
             rep["bad"].append((v, s, "choice %d out of range" % k_g))
             continue
         c_o_at_g = orc.sweep_cost(v, s, [1.0 / orc.level_q(v, s, k_g), 0, 0, 1])
-        if not close(float(C_g[g]), c_o_at_g):
+        if not close(float(C_g[g]), c_o_at_g, rel=rel, abs_=abs_):
             rep["bad"].append((v, s, "cost %.9g vs oracle %.9g at level %d" % (C_g[g], c_o_at_g, k_g)))
         d_o_at_g = 1.0 / orc.level_q(v, s, k_g)
         if abs(P_g[g, 0] - d_o_at_g) > DEPTH_REL * d_o_at_g or not np.allclose(P_g[g, 1:], [0, 0, 1]):
             rep["bad"].append((v, s, "plane %s vs depth %.9g" % (P_g[g], d_o_at_g)))
         if k_g != k_o:
             rep["mismatch_choice"] += 1
-            if m_o > MARGIN:
+            if m_o > margin:
                 rep["bad"].append((v, s, "level %d vs oracle %d with margin %.3g" % (k_g, k_o, m_o)))
-            elif c_o_at_g - c_o > MARGIN:
+            elif c_o_at_g - c_o > margin:
                 rep["bad"].append((v, s, "near-tie pick %.9g worse than best %.9g" % (c_o_at_g, c_o)))
             else:
                 rep["near_tie_flips"] += 1
-        if m_o > MARGIN and np.isfinite(M_g[g]) and M_g[g] < 0:
+        if m_o > margin and np.isfinite(M_g[g]) and M_g[g] < 0:
             rep["bad"].append((v, s, "negative margin"))
     return rep
 

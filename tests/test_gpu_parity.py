@@ -82,7 +82,7 @@ def test_superpixel_statistics(case):
 
 # ------------------------------------------------------------------ a2-a5: sweep
 
-@pytest.mark.parametrize("fmt", [0, 1, 2])
+@pytest.mark.parametrize("fmt", [0, 2])
 def test_sweep_parity_tiny(fmt):
     _say("sweep parity tiny, image format %d" % fmt)
     w = config1()
@@ -92,6 +92,27 @@ def test_sweep_parity_tiny(fmt):
     rep = parity.check_sweep(orc, ctx)
     _assert_clean(rep, "sweep fmt %d" % fmt)
     assert rep["n"] == 900
+
+
+def test_precision_form_sweep_and_depth_error():
+    """Precision form (FP16 texels, FP16 interpolation, FP32 accumulation):
+    normalised sweep cost within 1e-2 relative + 2e-4 absolute (FP16
+    rounding of the interpolated colour, <= 0.125 grey levels) and level
+    choices equal where the oracle's margin exceeds 5e-3; end-to-end depth
+    within 0.5 % (mean relative error) of the FP64 oracle after 3
+    refinement iterations."""
+    _say("precision form: tiny workload")
+    w = config1()
+    ctx = _ctx(w, image_precision=1)
+    orc = _oracle(w)
+    ctx.sweep()
+    rep = parity.check_sweep(orc, ctx, margin=5e-3, rel=1e-2, abs_=2e-4)
+    _assert_clean(rep, "precision-form sweep")
+    ctx.propagate(1, 3)
+    hist = orc.run(3)
+    errs = [parity.depth_mare(ctx.get_depth(v), orc.render_depth(hist[-1][0], v))[0] for v in range(orc.V)]
+    _say("precision form depth MARE per view: %s" % errs)
+    assert max(errs) <= parity.DEPTH_REL
 
 
 @pytest.mark.parametrize("case", ["ragged", "tiny_sp", "large_sp", "two_views", "one_level", "no_jitter",
