@@ -27,7 +27,7 @@ from typing import List
 import numpy as np
 
 from . import rig as rigmod
-from .scene import build_rig, grid_for, make_scene
+from .scene import build_rig, grid_for, make_scene, move_scene, scene_velocities
 
 
 @dataclass
@@ -116,6 +116,54 @@ def tiny_custom(W: int, H: int, gw: int, gh: int, *, n_views: int = 3, baseline:
     scene = make_scene(rng, f=f, W=W, H=H, sp_px=W * H / (gw * gh), n_rect=n_rect)
     rig = build_rig(views, scene, gw, gh, name="custom-%dx%dx%d" % (n_views, W, H), seed=seed, labels=labels)
     return Workload(rig.name, rig, MethodParams(levels=levels, iterations=iterations))
+
+
+class Sequence:
+    """Frames of a static rig filming a moving scene (the serving workload)."""
+
+    def __init__(self, name, views, scene, vel, gw, gh, params, seed):
+        self.name, self.views, self.scene, self.vel = name, views, scene, vel
+        self.gw, self.gh, self.params, self.seed = gw, gh, params, seed
+        self._cache = {}
+
+    def frame(self, k: int) -> rigmod.Rig:
+        if k not in self._cache:
+            views = [rigmod.View(K=v.K, R=v.R, t=v.t, W=v.W, H=v.H) for v in self.views]
+            self._cache[k] = build_rig(views, move_scene(self.scene, self.vel, k), self.gw, self.gh,
+                                       name="%s@%d" % (self.name, k), seed=self.seed)
+        return self._cache[k]
+
+
+def serving_rig(j: int, base_seed: int = 500, max_res: int = 3, max_views: int = 16,
+                image_precision: int = 1) -> Sequence:
+    """Rig j of the serving workload: drawn as in the batched recipe (views,
+    resolution, levels) with 0.05 grid spacing and FP16 texels; every
+    rectangle moves by U[-0.02, 0.02]^3 per frame, reflecting in depth
+    within [2.5, 7.5]."""
+    rng = np.random.Generator(np.random.PCG64(base_seed + j))
+    n = int(rng.integers(3, max_views + 1))
+    W, H = RESOLUTIONS[int(rng.integers(0, max_res))]
+    levels = int(rng.integers(128, 257))
+    f = 200.0 * W / 160.0
+    cols = int(math.ceil(math.sqrt(n)))
+    rows = int(math.ceil(n / cols))
+    views = rigmod.grid_rig(rows, cols, 0.05, f, W, H, n=n)
+    scene = make_scene(rng, f=f, W=W, H=H, sp_px=350.0, n_rect=3)
+    vel = scene_velocities(rng, scene)
+    gw, gh = grid_for(W, H, 350.0)
+    params = MethodParams(levels=levels, d_min=2.0, d_max=8.0, iterations=3)
+    return Sequence("serve%d-%dx%dx%d" % (j, n, W, H), views, scene, vel, gw, gh, params, base_seed + j)
+
+
+def tiny_sequence(seed: int = 11, W: int = 160, H: int = 120, gw: int = 20, gh: int = 15, n_views: int = 3,
+                  levels: int = 32, vmax: float = 0.02) -> Sequence:
+    """Small moving-scene sequence on a line rig, for tests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    views = rigmod.line_rig(n_views, 0.1, 200.0, W, H)
+    scene = make_scene(rng, f=200.0, W=W, H=H, sp_px=W * H / (gw * gh), n_rect=3)
+    vel = scene_velocities(rng, scene, vmax)
+    return Sequence("tinyseq-%dx%dx%d" % (n_views, W, H), views, scene, vel, gw, gh,
+                    MethodParams(levels=levels, iterations=2), seed)
 
 
 def by_name(name: str) -> Workload:

@@ -107,6 +107,29 @@ def make_scene(rng: np.random.Generator, *, f: float, W: int, H: int, sp_px: flo
             "n_low": n_low, "n_rect": n_rect}
 
 
+def scene_velocities(rng: np.random.Generator, scene: dict, vmax: float = 0.02) -> np.ndarray:
+    """Per-frame velocity of every rectangle centre, U[-vmax, vmax]^3; the background stays."""
+    v = rng.uniform(-vmax, vmax, size=(scene["rects"].shape[0], 3))
+    v[0] = 0.0
+    return v
+
+
+def move_scene(scene: dict, vel: np.ndarray, frame: int, z_lo: float = 2.5, z_hi: float = 7.5) -> dict:
+    """The scene at `frame`: rectangle j's centre moved by frame * vel[j], its depth
+    reflected back into [z_lo, z_hi] (a triangle wave); orientation, extent and
+    texture move with it."""
+    rects = scene["rects"].copy()
+    span = z_hi - z_lo
+    for j in range(1, rects.shape[0]):
+        p = rects[j, 0:3] + frame * vel[j]
+        u = (p[2] - z_lo) % (2.0 * span)
+        p[2] = z_lo + (u if u <= span else 2.0 * span - u)
+        rects[j, 0:3] = p
+    out = dict(scene)
+    out["rects"] = rects
+    return out
+
+
 def render_view(view: View, scene: dict) -> None:
     rgb, depth, pid = _native.raycast(view.W, view.H, view.K, view.R, view.t, scene["rects"], scene["tex_seeds"])
     view.rgb, view.gt_depth, view.gt_plane = rgb, depth, pid

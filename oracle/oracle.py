@@ -105,6 +105,38 @@ def make_params(mp) -> _Params:
                    int(g["term_mask"]), int(g["energy_mode"]))
 
 
+def warm_start_planes(Kinv, cen_prev, area_prev, A_prev, cen_new, area_new, d_min, d_max):
+    """Serving warm start (not in the paper, which treats frames independently):
+    the initial state of a new frame of a static rig from the previous frame's
+    state, cell by cell.
+
+    Kinv [S, 3, 3] inverse intrinsics of each cell's view; cen_* [S, 2]
+    centroids; area_* [S]; A_prev [S, 4] planes (d, n).  A cell that is
+    non-empty in both frames keeps its 3D plane n . X = delta, delta =
+    d_prev (n . K^-1 (c_prev, 1)), and takes the depth where the ray of its new
+    centroid meets that plane, d = delta / (n . K^-1 (c_new, 1)), if positive.
+    Otherwise (empty before, or no positive depth) it starts fronto-parallel at
+    d = 2 / (1/d_min + 1/d_max).  Cells empty now hold zeros."""
+    S = len(area_new)
+    out = np.zeros((S, 4))
+    d_fb = 2.0 / (1.0 / d_min + 1.0 / d_max)
+    for g in range(S):
+        if area_new[g] == 0:
+            continue
+        d_prev = A_prev[g, 0]
+        n = np.asarray(A_prev[g, 1:4], np.float64)
+        if area_prev[g] > 0 and d_prev > 0:
+            ray_prev = Kinv[g] @ np.array([cen_prev[g, 0], cen_prev[g, 1], 1.0])
+            ray_new = Kinv[g] @ np.array([cen_new[g, 0], cen_new[g, 1], 1.0])
+            delta = d_prev * float(n @ ray_prev)
+            t = float(n @ ray_new)
+            if t != 0.0 and delta / t > 0.0:
+                out[g] = [delta / t, n[0], n[1], n[2]]
+                continue
+        out[g] = [d_fb, 0.0, 0.0, 1.0]
+    return out
+
+
 class Oracle:
     """FP64 oracle bound to one rig.  Planes are float64 arrays [S_total, 4] = (d, nx, ny, nz)."""
 
@@ -255,6 +287,17 @@ class Oracle:
         out = np.empty((H, W))
         self._L.slfo_render_depth(self._c, _p(planes), view, _p(out))
         return out
+
+    def warm_start(self, prev: "Oracle", A_prev):
+        """Initial state of this rig's frame from `prev` (the same cameras and
+        grids, the previous frame) and its state A_prev; see warm_start_planes."""
+        area0, cen0, _ = prev.sp_stats()
+        area1, cen1, _ = self.sp_stats()
+        K = self._keep[4].reshape(-1, 3, 3)
+        Kinv = np.concatenate([np.repeat(np.linalg.inv(K[v])[None], int(self.sp_off[v + 1] - self.sp_off[v]), 0)
+                               for v in range(self.V)])
+        p = self._params
+        return warm_start_planes(Kinv, cen0, area0, np.asarray(A_prev, np.float64), cen1, area1, p.d_min, p.d_max)
 
     # -- convenience
     def view_slice(self, view):
