@@ -7,6 +7,11 @@ setup, the 256-level plane sweep of every superpixel of every view, 8
 refinement iterations over all views, and the depth readout of every view.
 
 Prints ONE JSON line (metric: SP-plane hypothesis evaluations per second).
+
+Other workloads (--workload): `precision` (4x4 rig at 720p, each image
+storage form timed and its end-to-end depth compared with the FP64 oracle's),
+`batched` (32 rigs of uneven size through one rig pool) and `serving` (6 rigs,
+Poisson frame arrivals, warm start, continuous batching; p50/p99 latency).
 """
 from __future__ import annotations
 
@@ -27,13 +32,42 @@ OPS_PER_SAMPLE_REFINE = 55.0
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
 
 
+def hbm_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated by a plain device copy), or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_fullhd_8view.json")
+    src = os.path.join(ROOT, "paper_1812_06856_amd", "csrc", "slf_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != sha:
+        return None
+    for name, k in rec["kernels"].items():
+        if name.endswith(kernel) or name.split("<")[0].endswith(kernel):
+            return k["read_bytes"] + k["write_bytes"]
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1024, help="superpixels in the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=8192, help="superpixels in the oracle's timed sample")
+    ap.add_argument("--workload", default="fullhd", choices=["fullhd", "precision", "batched", "serving"])
+    ap.add_argument("--rigs", type=int, default=32, help="batched: number of rigs")
+    ap.add_argument("--serve-rigs", type=int, default=6)
+    ap.add_argument("--serve-frames", type=int, default=6, help="serving: distinct frames rendered per rig")
+    ap.add_argument("--serve-rate", type=float, default=60.0, help="serving: mean arrivals per second, all rigs")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="serving: measured seconds")
+    ap.add_argument("--serve-warmup-s", type=float, default=3.0)
+    ap.add_argument("--serve-seed", type=int, default=5)
     ap.add_argument("--image-precision", type=int, default=0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
@@ -105,6 +139,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib)
+        return
+    if args.workload != "fullhd":
+        {"precision": run_precision, "batched": run_batched, "serving": run_serving}[args.workload](args)
         return
     import numpy as np
     import torch
@@ -223,13 +260,378 @@ def main():
         "stage_ms": {"setup": float(np.mean(t_setup)), "sweep": sweep_ms, "refine_total": ref_ms,
                      "refine_per_iteration": [float(np.mean(t)) for t in t_ref]},
         "roofline": {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": peak,
-                     "unit": "Tops/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "Tops/s", "frac": achieved / peak, "traffic": hbm_traffic(dom["kernel"]),
+                     "traffic_unit": "HBM bytes per launch",
                      "ops_per_sample": dom["ops_per_sample"], "launches_per_step": dom["launches"]},
     }
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, args.cpu_sample)
         cb.pop("seconds", None)
         out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+def _load_rig_inputs(ctx, w, dev, stream, image_precision):
+    """Cameras and params on ctx; images and labels copied to device tensors."""
+    import torch
+
+    from paper_1812_06856_amd import slf
+
+    vs = w.rig.views
+    ctx.set_cameras([(v.W, v.H) for v in vs], [v.K for v in vs], [v.R for v in vs], [v.t for v in vs])
+    ctx.set_params(slf.params_from(w.params, image_precision=image_precision))
+    with torch.cuda.stream(stream):
+        imgs = [torch.from_numpy(v.rgb).to(dev) for v in vs]
+        labs = [torch.from_numpy(v.labels).to(dev) for v in vs]
+        depth = [torch.empty((v.H, v.W), dtype=torch.float32, device=dev) for v in vs]
+    for i, v in enumerate(vs):
+        ctx.grids[i] = (v.gw, v.gh)
+    return imgs, labs, depth
+
+
+def run_precision(args):
+    """Precision form on the 4x4 720p workload (192 levels, 6 iterations): the
+    whole path timed with each image storage form (f32: the plain FP32 form;
+    f16: FP16 texels, FP32 accumulation, FP64 composition; u8: exact 8-bit
+    texels), alone and through a rig pool, and each form's end-to-end depth
+    maps compared with the FP64 oracle's.  The oracle's final planes come from
+    tests/golden/oracle_state_precision.npz (written by the oracle alone) and
+    are read out to depth by the oracle."""
+    import numpy as np
+    import torch
+
+    from lfsynth import config3
+    from paper_1812_06856_amd import slf
+
+    w = config3()
+    p = w.params
+    vs = w.rig.views
+    V = len(vs)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    ref_path = os.path.join(ROOT, "tests", "golden", "oracle_state_precision.npz")
+    orc_depth = None
+    if os.path.exists(ref_path):
+        from oracle.oracle import Oracle
+
+        ref = np.load(ref_path)
+        orc = Oracle(w.rig, p)
+        planes = ref["planes"].astype(np.float64)
+        orc_depth = [orc.render_depth(planes[orc.view_slice(v)], v) for v in range(V)]
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    forms = {}
+    for name, fmt in [("f32", slf.SLF_IMAGE_F32), ("f16", slf.SLF_IMAGE_F16), ("u8", slf.SLF_IMAGE_U8)]:
+        ctx = slf.Context(0)
+        ctx.set_stream(stream)
+        imgs, labs, depth = _load_rig_inputs(ctx, w, dev, stream, fmt)
+
+        def load():
+            for i, v in enumerate(vs):
+                ctx.set_image(i, imgs[i])
+                ctx.set_labels(i, labs[i], v.gw, v.gh)
+            ctx.prepare()
+
+        def solo():
+            load()
+            e0 = ev()
+            ctx.sweep()
+            ctx.propagate(1, p.iterations)
+            for i in range(V):
+                ctx.get_depth(i, out=depth[i])
+            return e0, ev()
+
+        for _ in range(args.warmup):
+            solo()
+        torch.cuda.synchronize()
+        ctx.reset_work()
+        marks = [solo() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        evals, samples = ctx.work()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in marks]))
+        d_solo = [depth[i].cpu().numpy() for i in range(V)]
+        pool = slf.Pool(0)
+        pool.set_stream(stream)
+        pool.attach(ctx)
+
+        def pooled():
+            load()
+            e0 = ev()
+            pool.submit(ctx, slf.SLF_POOL_SOLVE, 1, p.iterations, 0)
+            pool.run()
+            for i in range(V):
+                ctx.get_depth(i, out=depth[i])
+            return e0, ev()
+
+        for _ in range(args.warmup):
+            pooled()
+        pmarks = [pooled() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        pool.poll(64)
+        pool_ms = float(np.mean([a.elapsed_time(b) for a, b in pmarks]))
+        same = all(np.array_equal(d_solo[i], depth[i].cpu().numpy()) for i in range(V))
+        rec = {"ms_per_frame": ms, "ms_per_view": ms / V, "pooled_ms_per_frame": pool_ms,
+               "pooled_equals_solo": bool(same), "evals_per_s": evals / args.steps / (ms / 1e3),
+               "px_view_samples_per_s": samples / args.steps / (ms / 1e3)}
+        if orc_depth is not None:
+            rel = np.concatenate([np.abs(d_solo[i][m] - orc_depth[i][m]) / orc_depth[i][m]
+                                  for i in range(V) for m in [(orc_depth[i] > 0) & (d_solo[i] > 0)]])
+            rec.update({"depth_mare_vs_oracle": float(rel.mean()), "depth_p99_rel_vs_oracle": float(np.percentile(rel, 99)),
+                        "frac_px_over_0p5pct": float((rel > 5e-3).mean())})
+        forms[name] = rec
+        pool.close()
+        ctx.close()
+    out = {
+        "metric": "SP-plane hypothesis evals/s", "value": forms["f16"]["evals_per_s"], "unit": "evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": forms["f16"]["ms_per_frame"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "views": V, "resolution": "1280x720", "levels": p.levels,
+                   "iterations": p.iterations, "image_storage": "f16", "parallelism": "none"},
+        "forms": forms, "f16_vs_f32_speedup": forms["f32"]["ms_per_frame"] / forms["f16"]["ms_per_frame"],
+        "oracle_reference": os.path.relpath(ref_path, ROOT) if orc_depth is not None else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_batched(args):
+    """Batched form: 32 independent rigs (3-16 views, 640x480 to 1920x1080,
+    128-256 levels) solved together through one rig pool.  One step = every
+    rig's texel and superpixel setup, the pooled sweep and 3 pooled refinement
+    iterations (one HIP-graph replay of persistent launches) and the depth
+    readout of every view.  The same rigs run one after another through the
+    per-rig calls give the solo time beside it."""
+    import numpy as np
+    import torch
+
+    from lfsynth import configs
+    from paper_1812_06856_amd import slf
+
+    t_gen = time.perf_counter()
+    ws = [configs.rig_batched(j) for j in range(args.rigs)]
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    pool = slf.Pool(0)
+    pool.set_stream(stream)
+    ctxs, inputs = [], []
+    for w in ws:
+        c = slf.Context(0)
+        c.set_stream(stream)
+        inputs.append(_load_rig_inputs(c, w, dev, stream, args.image_precision))
+        ctxs.append(c)
+    stream.synchronize()
+
+    def load_and_prepare():
+        for c, w, (imgs, labs, _) in zip(ctxs, ws, inputs):
+            for i, v in enumerate(w.rig.views):
+                c.set_image(i, imgs[i])
+                c.set_labels(i, labs[i], v.gw, v.gh)
+            c.prepare()
+
+    def readout():
+        for c, (_, _, depth) in zip(ctxs, inputs):
+            for i in range(len(depth)):
+                c.get_depth(i, out=depth[i])
+
+    for c in ctxs:
+        pool.attach(c)
+    load_and_prepare()
+    t_tune = time.perf_counter()
+    pool.autotune()
+    t_tune = time.perf_counter() - t_tune
+    cfg = pool.get_config().as_dict()
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def pooled_step():
+        e0 = ev()
+        load_and_prepare()
+        e1 = ev()
+        for j, (c, w) in enumerate(zip(ctxs, ws)):
+            pool.submit(c, slf.SLF_POOL_SOLVE, 1, w.params.iterations, j)
+        pool.run()
+        e2 = ev()
+        readout()
+        e3 = ev()
+        return e0, e1, e2, e3
+
+    def solo_step():
+        e0 = ev()
+        load_and_prepare()
+        e1 = ev()
+        for c, w in zip(ctxs, ws):
+            c.sweep()
+            c.propagate(1, w.params.iterations)
+        e2 = ev()
+        readout()
+        e3 = ev()
+        return e0, e1, e2, e3
+
+    for _ in range(args.warmup):
+        pooled_step()
+        solo_step()
+    torch.cuda.synchronize()
+    for c in ctxs:
+        c.reset_work()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    marks = [pooled_step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pool.poll(4096)
+    evals = sum(c.work()[0] for c in ctxs)
+    samples = sum(c.work()[1] for c in ctxs)
+    solo = [solo_step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    step_ms = [m[0].elapsed_time(m[3]) for m in marks]
+    solve_ms = [m[1].elapsed_time(m[2]) for m in marks]
+    solo_solve_ms = [m[1].elapsed_time(m[2]) for m in solo]
+    ms = float(np.mean(step_ms))
+    n_views = sum(w.rig.n_views for w in ws)
+    out = {
+        "metric": "SP-plane hypothesis evals/s", "value": evals / args.steps / (ms / 1e3), "unit": "evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched-%drigs" % len(ws), "rigs": [w.rig.name for w in ws],
+                   "views": n_views, "levels": [w.params.levels for w in ws], "iterations": 3,
+                   "image_precision": args.image_precision, "parallelism": "none"},
+        "px_view_samples_per_s": samples / args.steps / (ms / 1e3),
+        "stage_ms": {"setup": float(np.mean([m[0].elapsed_time(m[1]) for m in marks])),
+                     "pooled_solve": float(np.mean(solve_ms)),
+                     "readout": float(np.mean([m[2].elapsed_time(m[3]) for m in marks])),
+                     "solo_solve": float(np.mean(solo_solve_ms))},
+        "pooled_vs_solo": float(np.mean(solo_solve_ms) / np.mean(solve_ms)),
+        "pool_config": cfg, "autotune_s": t_tune, "input_generation_s": t_gen,
+        "wall_s": dt,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serving(args):
+    """Serving form: 6 rigs drawn as in the batched workload (FP16 texels,
+    0.05 grid spacing) film moving scenes; frames arrive as one Poisson stream
+    (60 frames/s in total, rig chosen uniformly).  A rig's first frame is
+    solved in full (sweep + 3 iterations); later frames warm-start from the
+    rig's previous planes and run 2 iterations.  Requests share the pool and
+    join its stages as they come (continuous batching).  Latency = arrival to
+    the depth maps of all the frame's views in device memory."""
+    import collections
+
+    import numpy as np
+    import torch
+
+    from lfsynth import configs
+    from paper_1812_06856_amd import slf
+
+    t_gen = time.perf_counter()
+    seqs = [configs.serving_rig(j) for j in range(args.serve_rigs)]
+    F = args.serve_frames
+    frames = [[s.frame(k) for k in range(F)] for s in seqs]
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda:0")
+    pool = slf.Pool(0)
+    streams, ctxs, data, depth = [], [], [], []
+    for j, s in enumerate(seqs):
+        st = torch.cuda.Stream(device=dev)
+        c = slf.Context(0)
+        c.set_stream(st)
+        w0 = configs.Workload(s.name, frames[j][0], s.params)
+        _, _, dep = _load_rig_inputs(c, w0, dev, st, 1)
+        with torch.cuda.stream(st):
+            data.append([([torch.from_numpy(v.rgb).to(dev) for v in fr.views],
+                          [torch.from_numpy(v.labels).to(dev) for v in fr.views]) for fr in frames[j]])
+        streams.append(st)
+        ctxs.append(c)
+        depth.append(dep)
+        pool.attach(c)
+    torch.cuda.synchronize()
+    footprints = [c.footprint() for c in ctxs]
+
+    rng = np.random.default_rng(args.serve_seed)
+    horizon = args.serve_warmup_s + args.serve_seconds
+    arrivals = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / args.serve_rate)
+        if t >= horizon:
+            break
+        arrivals.append((t, int(rng.integers(0, len(seqs)))))
+    queue = [collections.deque() for _ in seqs]
+    n_frame = [0] * len(seqs)
+    busy = [None] * len(seqs)       # (arrival, tag) of the request in the pool
+    reading = {}                      # tag -> (rig, arrival, event) of depth readouts
+    latency = []
+    iters_warm = 2
+    tag = 0
+    a = 0
+    samples0 = sum(c.work()[1] for c in ctxs)
+    t0 = time.perf_counter()
+    while a < len(arrivals) or any(b is not None for b in busy) or reading or any(queue):
+        now = time.perf_counter() - t0
+        while a < len(arrivals) and arrivals[a][0] <= now:
+            queue[arrivals[a][1]].append(arrivals[a][0])
+            a += 1
+        for j, c in enumerate(ctxs):
+            if busy[j] is None and queue[j]:
+                arr = queue[j].popleft()
+                k = n_frame[j]
+                period = 2 * (F - 1)
+                fk = k % period if k % period < F else period - k % period  # 0 .. F-1 .. 1 ..
+                imgs, labs = data[j][fk]
+                for i, v in enumerate(frames[j][fk].views):
+                    c.set_image(i, imgs[i])
+                    c.set_labels(i, labs[i], v.gw, v.gh)
+                if k == 0:
+                    pool.submit(c, slf.SLF_POOL_SOLVE, 1, seqs[j].params.iterations, tag)
+                else:
+                    c.warm_start()
+                    pool.submit(c, slf.SLF_POOL_PROPAGATE, 1, iters_warm, tag)
+                busy[j] = (arr, tag)
+                n_frame[j] += 1
+                tag += 1
+        if pool.usage()["active"]:
+            pool.step()
+        for tg in pool.poll():
+            j = next(i for i, b in enumerate(busy) if b is not None and b[1] == tg)
+            arr = busy[j][0]
+            busy[j] = None
+            for i in range(len(depth[j])):
+                ctxs[j].get_depth(i, out=depth[j][i])
+            e = torch.cuda.Event()
+            e.record(streams[j])
+            reading[tg] = (j, arr, e)
+        for tg in list(reading):
+            j, arr, e = reading[tg]
+            if e.query():
+                done = time.perf_counter() - t0
+                if arr >= args.serve_warmup_s:
+                    latency.append((done - arr) * 1e3)
+                del reading[tg]
+        if not pool.usage()["active"] and not reading:
+            time.sleep(0.0002)
+    wall = time.perf_counter() - t0
+    samples = sum(c.work()[1] for c in ctxs) - samples0
+    lat = np.array(latency)
+    out = {
+        "metric": "served frame latency p99", "value": float(np.percentile(lat, 99)), "unit": "ms",
+        "n_gpus": 1, "steps": len(lat), "warmup": int(sum(1 for x in arrivals if x[0] < args.serve_warmup_s)),
+        "ms_per_step": float(np.mean(lat)), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "serving-%drigs" % len(seqs), "rigs": [s.name for s in seqs],
+                   "rate_fps": args.serve_rate, "seconds": args.serve_seconds, "warm_iterations": iters_warm,
+                   "image_precision": 1, "parallelism": "none"},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "max_ms": float(lat.max()), "frames": int(len(lat)), "offered_fps": args.serve_rate,
+        "px_view_samples_per_s": samples / wall, "footprint_bytes": footprints,
+        "input_generation_s": t_gen, "wall_s": wall,
+    }
     print(json.dumps(out), flush=True)
 
 

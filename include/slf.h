@@ -170,9 +170,109 @@ int slf_reset_work(slf_ctx *ctx);
 /* Waits for all work enqueued by the context. */
 int slf_synchronize(slf_ctx *ctx);
 
+/* Warm start for a new frame of a static rig: after new images and labels
+ * were set on the same cameras and label grids, each grid cell keeps its 3D
+ * plane from the previous frame's current state, with the depth taken at
+ * the cell's new centroid.  A cell that was empty in the previous frame, or
+ * whose plane does not face the camera at its new centroid, starts as the
+ * fronto-parallel plane at depth 2 / (1/d_min + 1/d_max).  Refinement then
+ * continues with slf_propagate, usually from I = 1.  (Not part of the paper,
+ * which processes frames independently (Sec. IV); a serving form.)
+ * SLF_ESTATE unless every view had planes when the new images or labels
+ * were set, with unchanged cameras and grids. */
+int slf_warm_start(slf_ctx *ctx);
+/* Device bytes the context holds once set up for its cameras, label grids
+ * and image precision (images, labels, texels, superpixel lists, plane
+ * state); the figure a pool admits against.  SLF_ESTATE before cameras and
+ * labels are set. */
+int slf_get_footprint(slf_ctx *ctx, uint64_t *bytes);
+
 const char *slf_status_string(int status);
 /* Message of the last failing call on ctx ("" if none); valid until the next call. */
 const char *slf_last_error(const slf_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Rig pool: many contexts ("rigs") driven together on one device.
+ *
+ * A pool accounts the footprint of attached rigs against an HBM budget
+ * (admission) and runs their work in stages.  A stage runs, for every
+ * active request, its next operation (the sweep or one refinement
+ * iteration); requests of the same operation and image format share one
+ * persistent launch whose waves pull (rig, superpixel-tile) items from a
+ * device work queue, XCD by XCD.  The arithmetic per superpixel is that of
+ * slf_sweep / slf_propagate, so a rig's results are identical whether it runs
+ * alone, through a pool, alone in a pool or in a mix.
+ *
+ * Ordering: a request's stages start after all work enqueued on the rig's
+ * stream before slf_pool_submit; once its last stage is launched, the rig's
+ * stream waits for it, so later calls on the rig see its result.  Between
+ * submit and the launch of its last stage every call on the rig returns
+ * SLF_ESTATE.  A pool is used by one host thread at a time.
+ * ---------------------------------------------------------------------- */
+typedef struct slf_pool slf_pool;
+
+enum {
+    SLF_POOL_SOLVE = 0,      /* the sweep, then the iterations */
+    SLF_POOL_PROPAGATE = 1   /* the iterations only, from the current planes */
+};
+
+/* Launch shape of pooled stages.  struct_size must be sizeof(slf_pool_config). */
+typedef struct {
+    int32_t struct_size;
+    int32_t sweep_level_chunk;  /* sweep levels scored per pass over the pixels: 4, 8 or 16 (default 8) */
+    int32_t sweep_tile;         /* superpixels per work item in sweep stages, 1..64 (default 1) */
+    int32_t refine_tile;        /* superpixels per work item in refinement stages, 1..64 (default 1) */
+    int32_t blocks_per_cu;      /* persistent workgroups per compute unit; 0 = as many as are resident */
+    int32_t use_graph;          /* 1: slf_pool_run captures its stage sequence as a HIP graph, replayed
+                                   while the sequence's shape repeats (default 1) */
+} slf_pool_config;
+
+void slf_pool_default_config(slf_pool_config *cfg);
+/* A pool on device_ordinal with hbm_budget_bytes of admission budget (0: the
+ * device's total memory) and a stream of its own. */
+int slf_pool_create(int device_ordinal, uint64_t hbm_budget_bytes, slf_pool **out);
+/* Waits for the pool's work, detaches every rig and frees the pool. */
+int slf_pool_destroy(slf_pool *pool);
+/* Runs the pool's work on `stream` (hipStream_t; NULL: the pool's own).
+ * SLF_ESTATE while requests are active. */
+int slf_pool_set_stream(slf_pool *pool, void *stream);
+int slf_pool_set_config(slf_pool *pool, const slf_pool_config *cfg);
+int slf_pool_get_config(slf_pool *pool, slf_pool_config *cfg);
+/* Admits a rig whose cameras and label grids are set: SLF_ENOMEM, with no
+ * change, if its footprint does not fit the budget left; SLF_EUNSUPPORTED
+ * beyond 64 rigs; SLF_ESTATE if it is attached already. */
+int slf_pool_attach(slf_pool *pool, slf_ctx *rig);
+/* Releases a rig's footprint; SLF_ESTATE while it has a request in flight. */
+int slf_pool_detach(slf_pool *pool, slf_ctx *rig);
+/* Budget, bytes admitted, rigs attached and requests active; NULL skips. */
+int slf_pool_usage(slf_pool *pool, uint64_t *budget, uint64_t *used, int *n_rigs, int *n_active);
+/* Queues a request for an attached rig (one at a time per rig): op
+ * SLF_POOL_SOLVE or SLF_POOL_PROPAGATE, iterations first_iter ..
+ * first_iter + n_iters - 1.  Builds the rig's superpixels if its inputs
+ * changed (synchronising the rig's stream).  Nothing is launched until
+ * slf_pool_step or slf_pool_run.  SLF_ENOMEM if the rig's footprint grew past
+ * the budget; SLF_ESTATE for PROPAGATE without planes. */
+int slf_pool_submit(slf_pool *pool, slf_ctx *rig, int op, int first_iter, int n_iters, uint64_t tag);
+/* Launches one stage of every active request; *n_active (may be NULL)
+ * receives the number still active afterwards.  Asynchronous. */
+int slf_pool_step(slf_pool *pool, int *n_active);
+/* Launches every active request to its end (one graph replay when
+ * use_graph = 1 and the schedule fits 64 groups, else stage by stage).
+ * Asynchronous. */
+int slf_pool_run(slf_pool *pool);
+/* Tags of requests whose work has completed (at most max per call, each
+ * reported once); does not block. */
+int slf_pool_poll(slf_pool *pool, uint64_t *done_tags, int max, int *n_done);
+/* Waits for all work launched by the pool. */
+int slf_pool_synchronize(slf_pool *pool);
+/* Picks sweep_level_chunk, sweep_tile and refine_tile by timing sweep and
+ * refinement stages over the attached rigs (each trial capped at 2048
+ * superpixels per rig), then keeps the fastest; results are cached per set of
+ * (resolution, neighbours, levels, precision, views) and *from_cache (may be
+ * NULL) is set to 1 on a hit.  Leaves every rig as after slf_sweep, with its
+ * work counters unchanged.  SLF_ESTATE while requests are active. */
+int slf_pool_autotune(slf_pool *pool, int *from_cache);
+const char *slf_pool_last_error(const slf_pool *pool);
 
 #ifdef __cplusplus
 }

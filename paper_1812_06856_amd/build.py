@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libslf.so")
-SOURCES = ["slf_api.hip", "slf_kernels.hip"]
+SOURCES = ["slf_api.hip", "slf_kernels.hip", "slf_pool.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

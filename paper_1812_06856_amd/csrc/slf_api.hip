@@ -13,25 +13,12 @@
 #include <vector>
 
 #include "slf.h"
+#include "slf_ctx.h"
 #include "slf_internal.h"
 
 using namespace slf;
 
 namespace {
-
-struct ViewHost {
-  int W = 0, H = 0;
-  double K[9], R[9], t[3], Kinv[9];
-  int gw = 0, gh = 0;
-  bool has_img = false, has_lab = false, has_planes = false;
-  std::vector<int> nbrs;
-};
-
-template <typename T>
-void dfree(T *&p) {
-  if (p) (void)hipFree((void *)p);
-  p = nullptr;
-}
 
 void inv3(const double *m, double *o) {
   const double a = m[0], b = m[1], c = m[2], d = m[3], e = m[4], f = m[5], g = m[6], h = m[7], i = m[8];
@@ -61,56 +48,6 @@ bool finite_all(const double *x, int n) {
 
 }  // namespace
 
-struct slf_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  slf_params p;
-  std::string err;
-  std::vector<ViewHost> vh;
-  int V = 0;
-
-  // per-pixel device buffers
-  uint8_t *d_rgb = nullptr;
-  int *d_labels = nullptr;
-  void *d_quads = nullptr;
-  size_t quads_bytes = 0;
-  int quads_fmt = -1;
-  bool quads_dirty = true;
-  int64_t total_px = 0;
-
-  // geometry tables
-  std::vector<ViewDev> views_h;
-  std::vector<PairDev> pairs_h;
-  ViewDev *d_views = nullptr;
-  PairDev *d_pairs = nullptr;
-  bool geom_dirty = true;
-
-  // superpixel buffers
-  int S = 0, S_cap = 0;
-  bool sp_dirty = true;
-  int *d_count = nullptr, *d_sp_view = nullptr, *d_area = nullptr, *d_px_off = nullptr, *d_scan = nullptr;
-  int *d_err = nullptr;
-  int4 *d_bbox = nullptr;
-  float2 *d_centroid = nullptr;
-  double2 *d_centroid_d = nullptr;
-  float4 *d_colour = nullptr;
-  PixEntry *d_px = nullptr;
-  float4 *d_planes[2] = {nullptr, nullptr};
-  float4 *d_tab[2] = {nullptr, nullptr};  // per superpixel {colour, inverse-depth row}
-  float *d_energy = nullptr, *d_margin = nullptr;
-  int *d_choice = nullptr;
-  unsigned long long *d_work = nullptr;
-  float *d_depth_tmp = nullptr;
-  int64_t depth_tmp_n = 0;
-  int cur = 0;
-  std::vector<int> area_h;
-  std::vector<double2> cen_h;
-  std::vector<float4> col_h;
-  uint64_t host_evals = 0, host_samples = 0;
-
-  int fail(int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
-};
-
 int slf_ctx::fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -120,14 +57,6 @@ int slf_ctx::fail(int code, const char *fmt, ...) {
   err = buf;
   return code;
 }
-
-#define HIP_OR_FAIL(ctx, call)                                                                          \
-  do {                                                                                                  \
-    hipError_t e_ = (call);                                                                             \
-    if (e_ != hipSuccess)                                                                               \
-      return (ctx)->fail(e_ == hipErrorOutOfMemory ? SLF_ENOMEM : SLF_EDEVICE, "%s: %s", #call,         \
-                         hipGetErrorString(e_));                                                        \
-  } while (0)
 
 namespace {
 
@@ -278,8 +207,11 @@ int build_geometry(slf_ctx *c) {
   return SLF_OK;
 }
 
-int alloc_sp(slf_ctx *c) {
-  if (c->S <= c->S_cap && c->d_px) return SLF_OK;
+// Superpixel buffers for c->S superpixels; *kept is set when the existing
+// buffers (and the plane state in them) were large enough to stay.
+int alloc_sp(slf_ctx *c, bool *kept) {
+  *kept = c->S <= c->S_cap && c->d_px;
+  if (*kept) return SLF_OK;
   free_sp(c);
   const size_t S = (size_t)c->S;
   const size_t nb = (S + 4095) / 4096 + 1;
@@ -305,14 +237,20 @@ int alloc_sp(slf_ctx *c) {
   return SLF_OK;
 }
 
+}  // namespace
+
 // Geometry tables, image texels and superpixel lists, rebuilt when inputs changed.
-int ensure_setup(slf_ctx *c) {
+int slf::ensure_setup(slf_ctx *c) {
   if (!views_ready(c)) return c->fail(SLF_ESTATE, "cameras, images and labels must be set for every view");
   int rc;
+  bool same_cells = true;  // every view keeps its grid cells (and so its plane state)
   if (c->geom_dirty) {
     const int old_S = c->S;
     if ((rc = build_geometry(c))) return rc;
-    if (c->S != old_S) c->sp_dirty = true;
+    if (c->S != old_S) {
+      c->sp_dirty = true;
+      same_cells = false;
+    }
   }
   const int fmt = c->p.image_precision;
   if (c->quads_dirty || c->quads_fmt != fmt) {
@@ -335,7 +273,11 @@ int ensure_setup(slf_ctx *c) {
     c->quads_dirty = false;
   }
   if (c->sp_dirty) {
-    if ((rc = alloc_sp(c))) return rc;
+    bool kept = false;
+    if ((rc = alloc_sp(c, &kept))) return rc;
+    bool all_planes = true;
+    for (const auto &v : c->vh) all_planes = all_planes && v.has_planes;
+    c->warm_ok = kept && same_cells && all_planes;
     HIP_OR_FAIL(c, launch_sp_build(c->d_views, c->views_h.data(), c->V, c->d_labels, c->d_rgb, c->S, c->d_count,
                                    c->d_bbox, c->d_px_off, c->d_scan, c->d_px, c->d_area, c->d_centroid,
                                    c->d_centroid_d, c->d_colour, c->d_sp_view, c->d_err, c->stream));
@@ -350,15 +292,120 @@ int ensure_setup(slf_ctx *c) {
     HIP_OR_FAIL(c, hipMemcpyAsync(c->cen_h.data(), c->d_centroid_d, sizeof(double2) * c->S, hipMemcpyDeviceToHost,
                                   c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-    if (herr & 1) return c->fail(SLF_EINVAL, "a label is outside [0, grid_w * grid_h)");
-    if (herr) return c->fail(SLF_EDEVICE, "superpixel list build inconsistent (flag %d)", herr);
     for (auto &v : c->vh) v.has_planes = false;
+    if (herr & 1) {
+      c->warm_ok = false;
+      return c->fail(SLF_EINVAL, "a label is outside [0, grid_w * grid_h)");
+    }
+    if (herr) return c->fail(SLF_EDEVICE, "superpixel list build inconsistent (flag %d)", herr);
     c->sp_dirty = false;
   }
   return SLF_OK;
 }
 
-}  // namespace
+int slf::footprint(const slf_ctx *c, uint64_t *bytes) {
+  if (c->V < 2) return SLF_ESTATE;
+  uint64_t px = 0, S = 0, pairs = 0, max_px = 0;
+  for (const auto &v : c->vh) {
+    if (v.gw < 1 || v.gh < 1) return SLF_ESTATE;
+    px += (uint64_t)v.W * v.H;
+    max_px = std::max<uint64_t>(max_px, (uint64_t)v.W * v.H);
+    S += (uint64_t)v.gw * v.gh;
+    pairs += v.nbrs.size();
+  }
+  uint64_t b = 0;
+  b += px * 3 + px * sizeof(int);                                 // images, labels
+  b += px * quad_bytes(c->p.image_precision);                     // bilinear texels
+  b += sizeof(ViewDev) * c->V + sizeof(PairDev) * pairs + 64;     // geometry, flags, counters
+  b += S * (4 * sizeof(int) + sizeof(int4) + sizeof(float2) + sizeof(double2) + sizeof(float4));
+  b += sizeof(int) * ((S + 4095) / 4096 + 2);                     // scan blocks, offsets
+  b += px * sizeof(PixEntry);                                     // pixel lists
+  b += S * 2 * (sizeof(float4) + 2 * sizeof(float4));             // plane state, ping-pong
+  b += S * (2 * sizeof(float) + sizeof(int));                     // energy, margin, choice
+  b += max_px * sizeof(float);                                    // host depth readout staging
+  *bytes = b;
+  return SLF_OK;
+}
+
+void slf::sweep_args(const slf_ctx *c, SweepArgs &a) {
+  a = SweepArgs{};
+  a.views = c->d_views;
+  a.pairs = c->d_pairs;
+  a.sp_view = c->d_sp_view;
+  a.area = c->d_area;
+  a.px_off = c->d_px_off;
+  a.px = c->d_px;
+  a.quads = c->d_quads;
+  a.S = c->S;
+  a.levels = c->p.levels;
+  a.qmin = 1.0 / c->p.d_max;
+  a.dq = (1.0 / c->p.d_min - 1.0 / c->p.d_max) / c->p.levels;
+  a.seed = c->p.seed;
+  a.jitter = c->p.jitter;
+  a.T255 = c->p.tssd_T * 255.f * 255.f;
+  a.planes = c->d_planes[c->cur];
+  a.colour = c->d_colour;
+  a.tab = c->d_tab[c->cur];
+  a.cost = c->d_energy;
+  a.choice = c->d_choice;
+  a.margin = c->d_margin;
+}
+
+void slf::after_sweep(slf_ctx *c) {
+  for (int v = 0; v < c->V; ++v) {
+    const ViewDev &d = c->views_h[v];
+    uint64_t nonempty = 0, px = 0;
+    for (int s = 0; s < d.gw * d.gh; ++s) {
+      const int A = c->area_h[d.sp_off + s];
+      nonempty += A > 0;
+      px += (uint64_t)A;
+    }
+    c->host_evals += nonempty * (uint64_t)c->p.levels;
+    c->host_samples += px * (uint64_t)d.n_pairs * (uint64_t)c->p.levels;
+    c->vh[v].has_planes = true;
+  }
+}
+
+void slf::refine_args(const slf_ctx *c, int iter, RefineArgs &a) {
+  a = RefineArgs{};
+  a.views = c->d_views;
+  a.pairs = c->d_pairs;
+  a.sp_view = c->d_sp_view;
+  a.area = c->d_area;
+  a.px_off = c->d_px_off;
+  a.px = c->d_px;
+  a.centroid_d = c->d_centroid_d;
+  a.colour = c->d_colour;
+  a.labels = c->d_labels;
+  a.quads = c->d_quads;
+  a.energy = c->d_energy;
+  a.choice = c->d_choice;
+  a.margin = c->d_margin;
+  a.work = c->d_work;
+  a.S = c->S;
+  a.kernel_step = c->p.kernel_step;
+  a.energy_mode = c->p.energy_mode;
+  a.term_mask = c->p.term_mask;
+  a.inv2sig2 = 1.f / (2.f * c->p.sigma * c->p.sigma);
+  a.inv2alpha2 = 1.f / (2.f * c->p.alpha * c->p.alpha);
+  a.inv2sig2_log2e = (float)(1.4426950408889634 / (2.0 * (double)c->p.sigma * (double)c->p.sigma));
+  a.inv2alpha2_log2e = (float)(1.4426950408889634 / (2.0 * (double)c->p.alpha * (double)c->p.alpha));
+  a.eta = c->p.eta;
+  a.occ_tol = c->p.occ_tol;
+  a.T255 = c->p.tssd_T * 255.f * 255.f;
+  a.iter = iter;
+  a.planesA = c->d_planes[c->cur];
+  a.tabA = c->d_tab[c->cur];
+  a.planesB = c->d_planes[1 - c->cur];
+  a.tabB = c->d_tab[1 - c->cur];
+}
+
+void slf::after_refine(slf_ctx *c) { c->cur = 1 - c->cur; }
+
+int slf::check_idle(slf_ctx *c) {
+  if (c->in_flight) return c->fail(SLF_ESTATE, "the rig has pool work not yet launched");
+  return SLF_OK;
+}
 
 // ===================================================================== C ABI
 
@@ -427,6 +474,7 @@ int slf_create(int device_ordinal, slf_ctx **out) {
 
 int slf_destroy(slf_ctx *c) {
   if (!c) return SLF_EINVAL;
+  if (c->pool) return c->fail(SLF_ESTATE, "detach the rig from its pool first");
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   free_all(c);
@@ -436,12 +484,14 @@ int slf_destroy(slf_ctx *c) {
 
 int slf_set_stream(slf_ctx *c, void *stream) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   c->stream = (hipStream_t)stream;
   return SLF_OK;
 }
 
 int slf_set_params(slf_ctx *c, const slf_params *p) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   int rc = params_check(c, p);
   if (rc) return rc;
   const bool radius_changed = p->kernel_radius_init != c->p.kernel_radius_init;
@@ -452,6 +502,7 @@ int slf_set_params(slf_ctx *c, const slf_params *p) {
 
 int slf_set_cameras(slf_ctx *c, int n_views, const int32_t *wh, const double *K, const double *R, const double *t) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   if (n_views < 2 || n_views > 4096) return c->fail(SLF_EINVAL, "n_views %d out of [2, 4096]", n_views);
   if (!wh || !K || !R || !t) return c->fail(SLF_EINVAL, "NULL camera array");
   std::vector<ViewHost> vh(n_views);
@@ -511,6 +562,7 @@ int slf_set_cameras(slf_ctx *c, int n_views, const int32_t *wh, const double *K,
 
 int slf_set_neighbors(slf_ctx *c, int view, int n, const int32_t *views) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
   if (n < 1 || n > c->V - 1 || !views) return c->fail(SLF_EINVAL, "need 1 <= n <= n_views - 1 neighbour views");
   std::vector<int> nb(views, views + n);
@@ -532,6 +584,7 @@ static int64_t pix_off_of(const slf_ctx *c, int view) {
 
 int slf_set_image_rgb8(slf_ctx *c, int view, const uint8_t *rgb, int64_t stride, int is_device) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
   const ViewHost &h = c->vh[view];
   if (!rgb) return c->fail(SLF_EINVAL, "rgb is NULL");
@@ -549,6 +602,7 @@ int slf_set_image_rgb8(slf_ctx *c, int view, const uint8_t *rgb, int64_t stride,
 
 int slf_set_labels(slf_ctx *c, int view, const int32_t *labels, int64_t stride, int gw, int gh, int is_device) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
   const ViewHost &h = c->vh[view];
   if (!labels) return c->fail(SLF_EINVAL, "labels is NULL");
@@ -579,54 +633,27 @@ int slf_set_labels(slf_ctx *c, int view, const int32_t *labels, int64_t stride, 
 
 int slf_prepare(slf_ctx *c) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   return ensure_setup(c);
 }
 
 int slf_sweep(slf_ctx *c) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   int rc = ensure_setup(c);
   if (rc) return rc;
-  SweepArgs a{};
-  a.views = c->d_views;
-  a.pairs = c->d_pairs;
-  a.sp_view = c->d_sp_view;
-  a.area = c->d_area;
-  a.px_off = c->d_px_off;
-  a.px = c->d_px;
-  a.quads = c->d_quads;
-  a.S = c->S;
-  a.levels = c->p.levels;
-  a.qmin = 1.0 / c->p.d_max;
-  a.dq = (1.0 / c->p.d_min - 1.0 / c->p.d_max) / c->p.levels;
-  a.seed = c->p.seed;
-  a.jitter = c->p.jitter;
-  a.T255 = c->p.tssd_T * 255.f * 255.f;
-  a.planes = c->d_planes[c->cur];
-  a.colour = c->d_colour;
-  a.tab = c->d_tab[c->cur];
-  a.cost = c->d_energy;
-  a.choice = c->d_choice;
-  a.margin = c->d_margin;
+  SweepArgs a;
+  sweep_args(c, a);
   HIP_OR_FAIL(c, launch_sweep(c->p.image_precision, a, c->stream));
-  for (int v = 0; v < c->V; ++v) {
-    const ViewDev &d = c->views_h[v];
-    uint64_t nonempty = 0, px = 0;
-    for (int s = 0; s < d.gw * d.gh; ++s) {
-      const int A = c->area_h[d.sp_off + s];
-      nonempty += A > 0;
-      px += (uint64_t)A;
-    }
-    c->host_evals += nonempty * (uint64_t)c->p.levels;
-    c->host_samples += px * (uint64_t)d.n_pairs * (uint64_t)c->p.levels;
-    c->vh[v].has_planes = true;
-  }
+  after_sweep(c);
   return SLF_OK;
 }
 
 int slf_set_planes(slf_ctx *c, int view, const float *planes) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
   if (!planes) return c->fail(SLF_EINVAL, "planes is NULL");
   HIP_OR_FAIL(c, hipSetDevice(c->device));
@@ -672,52 +699,47 @@ int slf_set_planes(slf_ctx *c, int view, const float *planes) {
 
 int slf_propagate(slf_ctx *c, int first_iter, int n_iters) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   if (first_iter < 1 || n_iters < 0) return c->fail(SLF_EINVAL, "need first_iter >= 1 and n_iters >= 0");
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   int rc = ensure_setup(c);
   if (rc) return rc;
   for (const auto &v : c->vh)
     if (!v.has_planes) return c->fail(SLF_ESTATE, "every view needs planes (slf_sweep or slf_set_planes)");
-  RefineArgs a{};
-  a.views = c->d_views;
-  a.pairs = c->d_pairs;
-  a.sp_view = c->d_sp_view;
-  a.area = c->d_area;
-  a.px_off = c->d_px_off;
-  a.px = c->d_px;
-  a.centroid_d = c->d_centroid_d;
-  a.colour = c->d_colour;
-  a.labels = c->d_labels;
-  a.quads = c->d_quads;
-  a.energy = c->d_energy;
-  a.choice = c->d_choice;
-  a.margin = c->d_margin;
-  a.work = c->d_work;
-  a.S = c->S;
-  a.kernel_step = c->p.kernel_step;
-  a.energy_mode = c->p.energy_mode;
-  a.term_mask = c->p.term_mask;
-  a.inv2sig2 = 1.f / (2.f * c->p.sigma * c->p.sigma);
-  a.inv2alpha2 = 1.f / (2.f * c->p.alpha * c->p.alpha);
-  a.inv2sig2_log2e = (float)(1.4426950408889634 / (2.0 * (double)c->p.sigma * (double)c->p.sigma));
-  a.inv2alpha2_log2e = (float)(1.4426950408889634 / (2.0 * (double)c->p.alpha * (double)c->p.alpha));
-  a.eta = c->p.eta;
-  a.occ_tol = c->p.occ_tol;
-  a.T255 = c->p.tssd_T * 255.f * 255.f;
   for (int it = first_iter; it < first_iter + n_iters; ++it) {
-    a.iter = it;
-    a.planesA = c->d_planes[c->cur];
-    a.tabA = c->d_tab[c->cur];
-    a.planesB = c->d_planes[1 - c->cur];
-    a.tabB = c->d_tab[1 - c->cur];
+    RefineArgs a;
+    refine_args(c, it, a);
     HIP_OR_FAIL(c, launch_refine(c->p.image_precision, a, c->stream));
-    c->cur = 1 - c->cur;
+    after_refine(c);
   }
+  return SLF_OK;
+}
+
+int slf_warm_start(slf_ctx *c) {
+  if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  int rc = ensure_setup(c);
+  if (rc) return rc;
+  if (!c->warm_ok)
+    return c->fail(SLF_ESTATE, "no previous plane state on these cameras and grids to start from");
+  const double q_mid = 0.5 * (1.0 / c->p.d_min + 1.0 / c->p.d_max);
+  HIP_OR_FAIL(c, launch_warm(c->d_views, c->d_sp_view, c->d_area, c->d_centroid_d, c->d_colour, c->d_planes[c->cur],
+                             c->d_tab[c->cur], c->S, 1.0 / q_mid, c->stream));
+  for (auto &v : c->vh) v.has_planes = true;
+  c->warm_ok = false;
+  return SLF_OK;
+}
+
+int slf_get_footprint(slf_ctx *c, uint64_t *bytes) {
+  if (!c || !bytes) return SLF_EINVAL;
+  if (footprint(c, bytes)) return c->fail(SLF_ESTATE, "cameras and label grids must be set first");
   return SLF_OK;
 }
 
 int slf_get_planes(slf_ctx *c, int view, float *planes, float *energy, int32_t *choice, float *margin) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
   if (c->sp_dirty || c->views_h.empty() || !c->vh[view].has_planes)
     return c->fail(SLF_ESTATE, "no planes for view %d", view);
@@ -739,6 +761,7 @@ int slf_get_planes(slf_ctx *c, int view, float *planes, float *energy, int32_t *
 
 int slf_get_depth(slf_ctx *c, int view, float *out, int64_t stride, int is_device) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
   if (!out) return c->fail(SLF_EINVAL, "out is NULL");
   if (c->sp_dirty || c->views_h.empty() || !c->vh[view].has_planes)
@@ -766,6 +789,7 @@ int slf_get_depth(slf_ctx *c, int view, float *out, int64_t stride, int is_devic
 
 int slf_get_superpixels(slf_ctx *c, int view, int32_t *area, float *centroid, float *colour) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
   if (c->sp_dirty || c->views_h.empty()) return c->fail(SLF_ESTATE, "superpixels not built yet");
   HIP_OR_FAIL(c, hipSetDevice(c->device));
@@ -788,6 +812,7 @@ int slf_get_superpixels(slf_ctx *c, int view, int32_t *area, float *centroid, fl
 
 int slf_get_work(slf_ctx *c, uint64_t *evals, uint64_t *samples) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   unsigned long long w[2] = {0, 0};
   HIP_OR_FAIL(c, hipMemcpyAsync(w, c->d_work, sizeof w, hipMemcpyDeviceToHost, c->stream));
@@ -799,6 +824,7 @@ int slf_get_work(slf_ctx *c, uint64_t *evals, uint64_t *samples) {
 
 int slf_reset_work(slf_ctx *c) {
   if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   HIP_OR_FAIL(c, hipMemsetAsync(c->d_work, 0, 2 * sizeof(unsigned long long), c->stream));
   c->host_evals = c->host_samples = 0;

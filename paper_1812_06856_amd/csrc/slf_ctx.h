@@ -1,0 +1,119 @@
+// Host-side state of one rig (slf_ctx) and the helpers that the per-rig
+// entry points (slf_api.hip) and the pool (slf_pool.hip) share.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "slf.h"
+#include "slf_internal.h"
+
+struct slf_pool;
+
+namespace slf {
+
+struct ViewHost {
+  int W = 0, H = 0;
+  double K[9], R[9], t[3], Kinv[9];
+  int gw = 0, gh = 0;
+  bool has_img = false, has_lab = false, has_planes = false;
+  std::vector<int> nbrs;
+};
+
+template <typename T>
+void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+}  // namespace slf
+
+struct slf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  slf_params p;
+  std::string err;
+  std::vector<slf::ViewHost> vh;
+  int V = 0;
+
+  // per-pixel device buffers
+  uint8_t *d_rgb = nullptr;
+  int *d_labels = nullptr;
+  void *d_quads = nullptr;
+  size_t quads_bytes = 0;
+  int quads_fmt = -1;
+  bool quads_dirty = true;
+  int64_t total_px = 0;
+
+  // geometry tables
+  std::vector<slf::ViewDev> views_h;
+  std::vector<slf::PairDev> pairs_h;
+  slf::ViewDev *d_views = nullptr;
+  slf::PairDev *d_pairs = nullptr;
+  bool geom_dirty = true;
+
+  // superpixel buffers
+  int S = 0, S_cap = 0;
+  bool sp_dirty = true;
+  int *d_count = nullptr, *d_sp_view = nullptr, *d_area = nullptr, *d_px_off = nullptr, *d_scan = nullptr;
+  int *d_err = nullptr;
+  int4 *d_bbox = nullptr;
+  float2 *d_centroid = nullptr;
+  double2 *d_centroid_d = nullptr;
+  float4 *d_colour = nullptr;
+  slf::PixEntry *d_px = nullptr;
+  float4 *d_planes[2] = {nullptr, nullptr};
+  float4 *d_tab[2] = {nullptr, nullptr};  // per superpixel {colour, inverse-depth row}
+  float *d_energy = nullptr, *d_margin = nullptr;
+  int *d_choice = nullptr;
+  unsigned long long *d_work = nullptr;
+  float *d_depth_tmp = nullptr;
+  int64_t depth_tmp_n = 0;
+  int cur = 0;
+  std::vector<int> area_h;
+  std::vector<double2> cen_h;
+  std::vector<float4> col_h;
+  uint64_t host_evals = 0, host_samples = 0;
+
+  // Warm start: every view had planes when the superpixels were last rebuilt
+  // for new images on the same cameras and grids.
+  bool warm_ok = false;
+
+  // pool membership
+  slf_pool *pool = nullptr;
+  uint64_t pool_bytes = 0;  // footprint accounted to the pool
+  bool in_flight = false;   // a pool request has stages not yet launched
+
+  int fail(int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+};
+
+#define HIP_OR_FAIL(ctx, call)                                                                          \
+  do {                                                                                                  \
+    hipError_t e_ = (call);                                                                             \
+    if (e_ != hipSuccess)                                                                               \
+      return (ctx)->fail(e_ == hipErrorOutOfMemory ? SLF_ENOMEM : SLF_EDEVICE, "%s: %s", #call,         \
+                         hipGetErrorString(e_));                                                        \
+  } while (0)
+
+namespace slf {
+
+// Geometry tables, image texels and superpixel lists, rebuilt when inputs
+// changed (slf_api.hip).  Synchronises the rig's stream when it rebuilds.
+int ensure_setup(slf_ctx *c);
+// Device bytes the rig holds once set up: images, labels, texels, geometry,
+// superpixel lists and plane state.  Needs cameras and label grids.
+int footprint(const slf_ctx *c, uint64_t *bytes);
+// Kernel arguments of a sweep / of refinement iteration `iter` on the rig's
+// current state (planes[cur] -> planes[1 - cur]).
+void sweep_args(const slf_ctx *c, SweepArgs &a);
+void refine_args(const slf_ctx *c, int iter, RefineArgs &a);
+// Bookkeeping after a sweep / an iteration was enqueued.
+void after_sweep(slf_ctx *c);
+void after_refine(slf_ctx *c);
+// SLF_ESTATE when the rig has pool stages not yet launched.
+int check_idle(slf_ctx *c);
+
+}  // namespace slf

@@ -95,6 +95,28 @@ struct RefineArgs {
   float inv2sig2_log2e, inv2alpha2_log2e;  // the same scales times log2(e), for exp2
 };
 
+// One rig's work in a pooled persistent launch: a sweep or one refinement
+// iteration over the rig's superpixels, cut into items of `tile` superpixels.
+enum { SLF_OP_SWEEP = 0, SLF_OP_REFINE = 1 };
+struct PoolJob {
+  int item_begin;  // first work item of this job within the stage
+  int S;           // superpixels of the rig
+  int pad[2];
+  SweepArgs sweep;     // used by sweep stages
+  RefineArgs refine;   // used by refinement stages
+};
+constexpr int kPoolQueues = 8;      // one per XCD
+constexpr int kPoolMaxJobs = 64;    // rigs in one stage
+constexpr int kPoolCounterStride = 16;  // ints between claim counters (one 64-byte line each)
+// A stage: every job runs the same op in the same image format.  Items
+// [qbegin[q], qend[q]) form queue q; the waves of XCD q drain it first.
+// Read-only while the stage runs; the claim counters live elsewhere.
+struct PoolStage {
+  int njobs, tile, pad[2];
+  int qbegin[kPoolQueues], qend[kPoolQueues];
+  PoolJob jobs[kPoolMaxJobs];
+};
+
 // Host-side launchers (slf_kernels.hip).
 hipError_t launch_quads(int fmt, const uint8_t *rgb, int64_t rgb_stride, int W, int H, void *quads,
                         int64_t quad_off, hipStream_t st);
@@ -107,5 +129,12 @@ hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st);
 hipError_t launch_depth(const ViewDev *views_d, const ViewDev &vh, int view, const int *labels,
                         const float4 *tab, float *out, int64_t stride, hipStream_t st);
 size_t quad_bytes(int fmt);
+hipError_t launch_warm(const ViewDev *views, const int *sp_view, const int *area, const double2 *cen,
+                       const float4 *colour, float4 *planes, float4 *tab, int S, double d_fb, hipStream_t st);
+// One pooled stage: a kernel that clears the stage's claim counters, then
+// the persistent kernel over `blocks` workgroups.
+hipError_t launch_pool(int op, int fmt, int kc, const PoolStage *stage, int *counters, int blocks, hipStream_t st);
+// Workgroups of the pooled kernel resident per compute unit.
+int pool_occupancy(int op, int fmt, int kc);
 
 }  // namespace slf

@@ -12,8 +12,20 @@
 
 namespace slf {
 
-__constant__ int kRingDx[8] = {1, 1, 0, -1, -1, -1, 0, 1};
-__constant__ int kRingDy[8] = {0, 1, 1, 1, 0, -1, -1, -1};
+// Ring R8 around a grid cell (gy pointing down); entry j + 1 is adjacent to
+// entry j.  Kept as 2-bit fields (offset + 1) of one constant, so a lane's
+// offset is a shift and a mask rather than a table load.
+constexpr int kRingDxTab[8] = {1, 1, 0, -1, -1, -1, 0, 1};
+constexpr int kRingDyTab[8] = {0, 1, 1, 1, 0, -1, -1, -1};
+constexpr unsigned pack_ring(const int *d) {
+  unsigned p = 0;
+  for (int j = 0; j < 8; ++j) p |= (unsigned)(d[j] + 1) << (2 * j);
+  return p;
+}
+constexpr unsigned kRingDxBits = pack_ring(kRingDxTab);
+constexpr unsigned kRingDyBits = pack_ring(kRingDyTab);
+__device__ __forceinline__ int ring_dx(int j) { return (int)((kRingDxBits >> (2 * j)) & 3u) - 1; }
+__device__ __forceinline__ int ring_dy(int j) { return (int)((kRingDyBits >> (2 * j)) & 3u) - 1; }
 
 // ------------------------------------------------------------------ helpers
 
@@ -77,22 +89,26 @@ __device__ __forceinline__ long long wave_sum_ll(long long x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
   return x;
 }
-__device__ __forceinline__ float wave_min(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o, kWave));
-  return x;
+// Reductions over the ring lanes 0..7, read from lane 0 (uniform result):
+// quad xor 1, quad xor 2, half-row mirror.  Lanes 8.. do not take part; the
+// whole wave must be active.
+__device__ __forceinline__ float ring_min(float x) {
+  x = fminf(x, dpp_f<kDppXor1>(x));
+  x = fminf(x, dpp_f<kDppXor2>(x));
+  x = fminf(x, dpp_f<kDppHalfMirror>(x));
+  return rd_f(x, 0);
 }
-__device__ __forceinline__ float wave_max(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, kWave));
-  return x;
+__device__ __forceinline__ float ring_max(float x) {
+  x = fmaxf(x, dpp_f<kDppXor1>(x));
+  x = fmaxf(x, dpp_f<kDppXor2>(x));
+  x = fmaxf(x, dpp_f<kDppHalfMirror>(x));
+  return rd_f(x, 0);
 }
-// Sum over lanes 0..7 (other lanes must contribute 0), broadcast to all lanes.
 __device__ __forceinline__ float ring_sum(float x) {
-  x += __shfl_xor(x, 4, kWave);
-  x += __shfl_xor(x, 2, kWave);
-  x += __shfl_xor(x, 1, kWave);
-  return __shfl(x, 0, kWave);
+  x += dpp_f<kDppXor1>(x);
+  x += dpp_f<kDppXor2>(x);
+  x += dpp_f<kDppHalfMirror>(x);
+  return rd_f(x, 0);
 }
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -489,12 +505,8 @@ __host__ __device__ inline int launch_blocks(int nblocks) {
 // summed by a butterfly and the running argmin keeps the smallest level on
 // ties.
 template <int FMT, int KC>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
+__device__ __forceinline__ void sweep_sp(const SweepArgs &a, const int g) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int blk = logical_block((a.S + kWavesPerBlock - 1) / kWavesPerBlock);
-  if (blk < 0) return;
-  const int g = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + (threadIdx.x >> 6));
-  if (g >= a.S) return;
   const int v = a.sp_view[g];
   const ViewDev &vw = a.views[v];
   const int s = g - vw.sp_off;
@@ -595,6 +607,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
 #endif
 constexpr int kLevelChunk = SLF_LEVEL_CHUNK;
 
+template <int FMT, int KC>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
+  const int blk = logical_block((a.S + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (blk < 0) return;
+  const int g = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + (threadIdx.x >> 6));
+  if (g >= a.S) return;
+  sweep_sp<FMT, KC>(a, g);
+}
+
 hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st) {
   const dim3 grid(launch_blocks((a.S + kWavesPerBlock - 1) / kWavesPerBlock)), block(kBlock);
   switch (fmt) {
@@ -610,11 +631,18 @@ hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st) {
 
 constexpr int kLdsPix = 1024;  // pixels of a superpixel staged in LDS (the rest read from the list)
 
-// Neighbour views sampled together per pixel in the refinement energy.
-#ifndef SLF_VIEW_GROUP
-#define SLF_VIEW_GROUP 1
-#endif
-constexpr int kViewGroup = SLF_VIEW_GROUP;
+typedef __attribute__((address_space(3))) uint32_t LdsU32;
+
+// Raw buffer resource over `bytes` bytes at p (gfx9-family descriptor word 3):
+// loads past the end return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float3 load_f3(__amdgpu_buffer_rsrc_t rs, int off) {
+  typedef float f3v __attribute__((ext_vector_type(3)));
+  const f3v v = __builtin_bit_cast(f3v, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0));
+  return make_float3(v.x, v.y, v.z);
+}
 
 struct Best {
   float E, second;
@@ -629,7 +657,7 @@ struct SpCtx {
   int g, v, s, A, N, poff;
   int ub, vb;                // centroid rounded to the nearest pixel
   float invA;                // 1 / |Omega|
-  const uint32_t *pix_lds;   // the first kLdsPix pixels (u | v << 16), staged in LDS
+  const LdsU32 *pix_lds;     // the first kLdsPix pixels (u | v << 16), staged in LDS
   double rsx, rsy, rsz;      // K_r^-1 (c_s, 1)
   float4 Cs;                 // mean colour
   float omega_min;           // min over ring neighbours of omega(C_s, C_j); 1 without neighbours
@@ -746,93 +774,88 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         awv = (float)H[7];
       }
       const int nv = min(kWave, c.N - base);
-      // Views in groups of kViewGroup: a lane takes one pixel and samples it
-      // in every view of the group, so the group's label and table gathers
-      // are independent and in flight together.
-      for (int jv0 = 0; jv0 < nv; jv0 += kViewGroup) {
-        float cax[kViewGroup], caxu[kViewGroup], caxv[kViewGroup], cay[kViewGroup], cayu[kViewGroup],
-            cayv[kViewGroup], caw[kViewGroup], cawu[kViewGroup], cawv[kViewGroup], fX0[kViewGroup],
-            fY0[kViewGroup], Wm1[kViewGroup], Hm1[kViewGroup];
-        int Wv[kViewGroup], Km1[kViewGroup];
-        const int *lab[kViewGroup];
-        const float4 *tabv[kViewGroup];
-        float sw[kViewGroup], gx[kViewGroup];
-        int nX[kViewGroup];
-        bool anyY[kViewGroup];
-#pragma unroll
-        for (int k = 0; k < kViewGroup; ++k) {
-          const int jv = min(jv0 + k, nv - 1);
-          cax[k] = bcast(ax, jv);
-          caxu[k] = bcast(axu, jv);
-          caxv[k] = bcast(axv, jv);
-          cay[k] = bcast(ay, jv);
-          cayu[k] = bcast(ayu, jv);
-          cayv[k] = bcast(ayv, jv);
-          caw[k] = bcast(aw, jv);
-          cawu[k] = bcast(awu, jv);
-          cawv[k] = bcast(awv, jv);
-          fX0[k] = (float)__builtin_amdgcn_readlane(X0, jv);
-          fY0[k] = (float)__builtin_amdgcn_readlane(Y0, jv);
-          const ViewDev &vi = a.views[a.pairs[vw.pair_off + base + jv].i];
-          Wm1[k] = (float)(vi.W - 1);
-          Hm1[k] = (float)(vi.H - 1);
-          Wv[k] = vi.W;
-          Km1[k] = vi.gw * vi.gh - 1;
-          lab[k] = a.labels + vi.pix_off;
-          tabv[k] = a.tabA + 2 * vi.sp_off;
-          sw[k] = 0.f;
-          gx[k] = 0.f;
-          nX[k] = 0;
-          anyY[k] = false;
-        }
-        const int ng = min(kViewGroup, nv - jv0);
-        // Branch-free samples: indices are clamped so the label and table
-        // loads are always in bounds; predicates decide what is accumulated.
-        for (int p = lane; p < c.A; p += kWave) {
-          const uint32_t uv = p < kLdsPix ? c.pix_lds[p] : a.px[c.poff + p].x;
+      for (int jv = 0; jv < nv; ++jv) {
+        // view jv's constants, uniform over the wave
+        const float cax = bcast(ax, jv), caxu = bcast(axu, jv), caxv = bcast(axv, jv);
+        const float cay = bcast(ay, jv), cayu = bcast(ayu, jv), cayv = bcast(ayv, jv);
+        const float caw = bcast(aw, jv), cawu = bcast(awu, jv), cawv = bcast(awv, jv);
+        const float fX0 = (float)__builtin_amdgcn_readlane(X0, jv), fY0 = (float)__builtin_amdgcn_readlane(Y0, jv);
+        const ViewDev &vi = a.views[a.pairs[vw.pair_off + base + jv].i];
+        const float Wm1 = (float)(vi.W - 1), Hm1 = (float)(vi.H - 1);
+        const uint32_t Wv = (uint32_t)vi.W;
+        const __amdgpu_buffer_rsrc_t lab_rs = buffer_rsrc(a.labels + vi.pix_off, 4u * (uint32_t)vi.W * (uint32_t)vi.H);
+        const __amdgpu_buffer_rsrc_t tab_rs = buffer_rsrc(a.tabA + 2 * vi.sp_off, 32u * (uint32_t)(vi.gw * vi.gh));
+        float sw = 0.f, gx = 0.f;
+        int nX = 0;
+        bool anyY = false;
+        // Branch-free samples in three phases: project the pixel into view
+        // i (clamped into the image), gather its label, gather the label's
+        // record; the gathers are raw buffer loads bounded by their arrays.
+        // Predicates decide what is accumulated.
+        struct Proj {
+          float iota, w, dx, dy;
+          bool seen;
+          uint32_t pix;
+        };
+        auto project = [&](uint32_t uv) {
+          Proj q;
           const float du = (float)((int)(uv & 0xffffu) - c.ub), dv = (float)((int)(uv >> 16) - c.vb);
-          const float iota = fmaf(gu, du, fmaf(gv, dv, i0));  // 1 / D(p)
-#pragma unroll
-          for (int k = 0; k < kViewGroup; ++k) {
-            if (k >= ng) break;
-            const float w = fmaf(cawu[k], du, fmaf(cawv[k], dv, caw[k]));  // z_i(P) = w / iota
-            const float rw = rcp(w);
-            const float dx = fmaf(caxu[k], du, fmaf(caxv[k], dv, cax[k])) * rw;
-            const float dy = fmaf(cayu[k], du, fmaf(cayv[k], dv, cay[k])) * rw;
-            const float uf = fX0[k] + floorf(dx + 0.5f), vf = fY0[k] + floorf(dy + 0.5f);
-            // clamp into the image (a NaN fails the equality and converts to 0)
-            const float uc = __builtin_amdgcn_fmed3f(uf, 0.f, Wm1[k]), vc = __builtin_amdgcn_fmed3f(vf, 0.f, Hm1[k]);
-            const bool seen = (iota > 0.f) & (w > 0.f) & (uc == uf) & (vc == vf);
-            const uint32_t pix = (uint32_t)(int)vc * (uint32_t)Wv[k] + (uint32_t)(int)uc;
-            const uint32_t l = (uint32_t)min(max(lab[k][pix], 0), Km1[k]);
-            const float4 Cl = tabv[k][2u * l];
-            const float4 gt = tabv[k][2u * l + 1u];
-            const float dr = c.Cs.x - Cl.x, dg = c.Cs.y - Cl.y, db = c.Cs.z - Cl.z;
-            const float om = __builtin_amdgcn_exp2f(-fmaf(db, db, fmaf(dg, dg, dr * dr)) * a.inv2alpha2_log2e);
-            const float den = fmaf(gt.x, fX0[k] + dx, fmaf(gt.y, fY0[k] + dy, gt.z));  // 1 / D(p^i)
-            const bool front = den > 0.f;
-            // z <= D(p^i) (1 + tau)  <=>  w den <= (1 + tau) iota   (iota, den > 0)
-            const float wd = w * den;
-            const bool vis = !front || (wd <= tol * iota);
-            const float dz = (wd - iota) * rcp(iota * den);  // z - D(p^i)
-            const float gk = __builtin_amdgcn_exp2f(-dz * dz * a.inv2sig2_log2e);
-            sw[k] += seen ? om : 0.f;
-            nX[k] += (seen & vis) ? 1 : 0;
-            gx[k] += (seen & vis & front) ? gk : 0.f;
-            anyY[k] |= seen & !vis;
-          }
+          q.iota = fmaf(gu, du, fmaf(gv, dv, i0));  // 1 / D(p)
+          q.w = fmaf(cawu, du, fmaf(cawv, dv, caw));  // z_i(P) = w / iota
+          const float rw = rcp(q.w);
+          q.dx = fmaf(caxu, du, fmaf(caxv, dv, cax)) * rw;
+          q.dy = fmaf(cayu, du, fmaf(cayv, dv, cay)) * rw;
+          const float uf = fX0 + floorf(q.dx + 0.5f), vf = fY0 + floorf(q.dy + 0.5f);
+          // clamp into the image (a NaN fails the equality and converts to 0)
+          const float uc = __builtin_amdgcn_fmed3f(uf, 0.f, Wm1), vc = __builtin_amdgcn_fmed3f(vf, 0.f, Hm1);
+          q.seen = (q.iota > 0.f) & (q.w > 0.f) & (uc == uf) & (vc == vf);
+          q.pix = (uint32_t)(int)vc * Wv + (uint32_t)(int)uc;
+          return q;
+        };
+        auto label = [&](const Proj &q) {
+          return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(lab_rs, (int)(4u * q.pix), 0, 0);
+        };
+        auto accumulate = [&](const Proj &q, const float3 Cl, const float3 gt) {
+          const float dr = c.Cs.x - Cl.x, dg = c.Cs.y - Cl.y, db = c.Cs.z - Cl.z;
+          const float om = __builtin_amdgcn_exp2f(-fmaf(db, db, fmaf(dg, dg, dr * dr)) * a.inv2alpha2_log2e);
+          const float den = fmaf(gt.x, fX0 + q.dx, fmaf(gt.y, fY0 + q.dy, gt.z));  // 1 / D(p^i)
+          const bool front = den > 0.f;
+          // z <= D(p^i) (1 + tau)  <=>  w den <= (1 + tau) iota   (iota, den > 0)
+          const float wd = q.w * den;
+          const bool vis = !front || (wd <= tol * q.iota);
+          const float dz = (wd - q.iota) * rcp(q.iota * den);  // z - D(p^i)
+          const float gk = __builtin_amdgcn_exp2f(-dz * dz * a.inv2sig2_log2e);
+          sw += q.seen ? om : 0.f;
+          nX += (q.seen & vis) ? 1 : 0;
+          gx += (q.seen & vis & front) ? gk : 0.f;
+          anyY |= q.seen & !vis;
+        };
+        auto one = [&](uint32_t uv) {
+          const Proj q = project(uv);
+          const uint32_t l = label(q);
+          accumulate(q, load_f3(tab_rs, (int)(32u * l)), load_f3(tab_rs, (int)(32u * l + 16u)));
+        };
+        // Two pixels per lane per pass keep two gather chains in flight;
+        // each lane still accumulates its pixels in order.
+        const int n_lds = min(c.A, kLdsPix);
+        int p = lane;
+        for (; p + kWave < n_lds; p += 2 * kWave) {
+          const Proj q0 = project(c.pix_lds[p]), q1 = project(c.pix_lds[p + kWave]);
+          const uint32_t l0 = label(q0), l1 = label(q1);
+          const float3 C0 = load_f3(tab_rs, (int)(32u * l0)), G0 = load_f3(tab_rs, (int)(32u * l0 + 16u));
+          const float3 C1 = load_f3(tab_rs, (int)(32u * l1)), G1 = load_f3(tab_rs, (int)(32u * l1 + 16u));
+          accumulate(q0, C0, G0);
+          accumulate(q1, C1, G1);
         }
-#pragma unroll
-        for (int k = 0; k < kViewGroup; ++k) {
-          if (k >= ng) break;
-          const float swt = wave_sum(sw[k]);
-          const float gxt = wave_sum(gx[k]);
-          const int nXt = wave_sum_i(nX[k]);
-          const bool Y = __ballot(anyY[k]) != 0ull;
-          const float Si = swt * c.invA;
-          const float Vi = nXt > 0 ? Si * gxt * rcp((float)nXt) : 0.f;
-          sum += Vi + (Y ? occ : 0.f);
-        }
+        if (p < n_lds) one(c.pix_lds[p]);
+        for (p = kLdsPix + lane; p < c.A; p += kWave) one(a.px[c.poff + p].x);
+        const float swt = wave_sum(sw);
+        const float gxt = wave_sum(gx);
+        const int nXt = wave_sum_i(nX);
+        const bool Y = __ballot(anyY) != 0ull;
+        const float Si = swt * c.invA;
+        const float Vi = nXt > 0 ? Si * gxt * rcp((float)nXt) : 0.f;
+        sum += Vi + (Y ? occ : 0.f);
       }
     }
     Ec = sum * rcp((float)c.N);
@@ -911,16 +934,8 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
 // Candidates are generated lane-parallel in slot order into an LDS list and
 // evaluated in that order by one energy loop.
 template <int FMT>
-__global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
-  __shared__ Cand s_list[kWavesPerBlock][kCandBatch];
-  __shared__ uint32_t s_pix[kWavesPerBlock][kLdsPix];
+__device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand *list, uint32_t *pix_lds) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x >> 6;
-  const int blk = logical_block((a.S + kWavesPerBlock - 1) / kWavesPerBlock);
-  if (blk < 0) return;
-  const int g = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + wid);
-  if (g >= a.S) return;
-  Cand *list = s_list[wid];
   SpCtx c;
   c.g = g;
   c.v = a.sp_view[g];
@@ -941,8 +956,8 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
   c.N = vw.n_pairs;
   c.poff = a.px_off[g];
   c.invA = 1.f / (float)c.A;
-  for (int p = lane; p < min(c.A, kLdsPix); p += kWave) s_pix[wid][p] = a.px[c.poff + p].x;
-  c.pix_lds = s_pix[wid];
+  for (int p = lane; p < min(c.A, kLdsPix); p += kWave) pix_lds[p] = a.px[c.poff + p].x;
+  c.pix_lds = (const LdsU32 *)pix_lds;
   wave_lds_sync();
   const double2 cs = a.centroid_d[g];
   ray_of(vw, cs, c.rsx, c.rsy, c.rsz);
@@ -957,7 +972,7 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
   c.ring_d = 0.0;
   float dist2 = INFINITY;
   if (lane < 8) {
-    const int x = gx + kRingDx[lane], y = gy + kRingDy[lane];
+    const int x = gx + ring_dx(lane), y = gy + ring_dy(lane);
     if (x >= 0 && x < vw.gw && y >= 0 && y < vw.gh) {
       const int k = y * vw.gw + x;
       const int gk = vw.sp_off + k;
@@ -972,8 +987,8 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
     }
   }
   c.M = __popcll(__ballot(c.ring_cell >= 0));
-  const float dmin2 = wave_min(dist2);
-  const float dmax2 = wave_max(c.ring_cell >= 0 ? dist2 : -INFINITY);
+  const float dmin2 = ring_min(dist2);
+  const float dmax2 = ring_max(c.ring_cell >= 0 ? dist2 : -INFINITY);
   c.ring_w = c.ring_cell >= 0 ? __expf(-(dist2 - dmin2) * a.inv2alpha2) : 0.f;
   c.omega_min = c.M > 0 ? __expf(-dmax2 * a.inv2alpha2) : 1.f;
 
@@ -1000,12 +1015,12 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
     if (r < n_raw) {
       int x = gx, y = gy;
       if (r >= 1 && r <= 8) {
-        x += kRingDx[r - 1];
-        y += kRingDy[r - 1];
+        x += ring_dx(r - 1);
+        y += ring_dy(r - 1);
       } else if (r >= 9) {
         const int m = a.kernel_step * ((r - 9) / 8 + 1), j = (r - 9) % 8;
-        x += m * kRingDx[j];
-        y += m * kRingDy[j];
+        x += m * ring_dx(j);
+        y += m * ring_dy(j);
       }
       if (x >= 0 && x < vw.gw && y >= 0 && y < vw.gh) {
         const int gk = vw.sp_off + y * vw.gw + x;
@@ -1100,6 +1115,18 @@ __global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
   }
 }
 
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
+  __shared__ Cand s_list[kWavesPerBlock][kCandBatch];
+  __shared__ uint32_t s_pix[kWavesPerBlock][kLdsPix];
+  const int wid = threadIdx.x >> 6;
+  const int blk = logical_block((a.S + kWavesPerBlock - 1) / kWavesPerBlock);
+  if (blk < 0) return;
+  const int g = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + wid);
+  if (g >= a.S) return;
+  refine_sp<FMT>(a, g, s_list[wid], s_pix[wid]);
+}
+
 hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st) {
   const dim3 grid(launch_blocks((a.S + kWavesPerBlock - 1) / kWavesPerBlock)), block(kBlock);
   switch (fmt) {
@@ -1107,6 +1134,144 @@ hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st) {
     case SLF_FMT_F16: hipLaunchKernelGGL((k_refine<SLF_FMT_F16>), grid, block, 0, st, a); break;
     default: hipLaunchKernelGGL((k_refine<SLF_FMT_F32>), grid, block, 0, st, a); break;
   }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ pooled persistent launch
+// Many rigs in one launch.  Work items (`tile` consecutive superpixels of
+// one job) are claimed from kPoolQueues queues; a wave drains the queue of
+// its own XCD (workgroup b runs on XCD b mod 8) and then steals from the
+// others in turn, so every wave exits once all queues are empty.  Each item
+// runs the same per-superpixel device functions as the per-rig kernels.
+__global__ void k_pool_reset(int *counters) {
+  if (threadIdx.x < kPoolQueues) counters[threadIdx.x * kPoolCounterStride] = 0;
+}
+
+typedef const __attribute__((address_space(4))) PoolStage ConstStage;
+
+template <int OP, int FMT, int KC>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SLF_OP_REFINE ? 4 : 1))) void k_pool(const PoolStage *__restrict__ stage_ptr, int *__restrict__ counters) {
+  __shared__ Cand s_list[OP == SLF_OP_REFINE ? kWavesPerBlock : 1][kCandBatch];
+  __shared__ uint32_t s_pix[OP == SLF_OP_REFINE ? kWavesPerBlock : 1][kLdsPix];
+  // The stage table does not change during the launch: read it through the
+  // constant address space, as kernel arguments are, so that its fields are
+  // loaded into scalar registers.
+  ConstStage &st = *(ConstStage *)stage_ptr;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = OP == SLF_OP_REFINE ? (int)(threadIdx.x >> 6) : 0;
+  const int home = (int)(blockIdx.x % kPoolQueues);
+  const int njobs = st.njobs, tile = st.tile;
+  for (int k = 0; k < kPoolQueues; ++k) {
+    const int q = (home + k) % kPoolQueues;
+    const int begin = st.qbegin[q], end = st.qend[q];
+    int *next = counters + q * kPoolCounterStride;
+    for (;;) {
+      int t = 0;
+      if (lane == 0) t = atomicAdd(next, 1);
+      const int item = begin + __builtin_amdgcn_readfirstlane(t);
+      if (item >= end) break;
+      int lo = 0, hi = njobs - 1;  // the job holding the item
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st.jobs[mid].item_begin <= item) lo = mid;
+        else hi = mid - 1;
+      }
+      lo = __builtin_amdgcn_readfirstlane(lo);
+      const PoolJob &J = *(const PoolJob *)&st.jobs[lo];
+      const int g0 = (item - J.item_begin) * tile;
+      const int g1 = min(g0 + tile, J.S);
+      for (int g = g0; g < g1; ++g) {
+        if constexpr (OP == SLF_OP_SWEEP)
+          sweep_sp<FMT, KC>(J.sweep, g);
+        else
+          refine_sp<FMT>(J.refine, g, s_list[wid], s_pix[wid]);
+      }
+    }
+  }
+}
+
+template <int OP, int FMT>
+static const void *pool_kernel(int kc) {
+  if constexpr (OP == SLF_OP_REFINE) {  // the refinement has no level chunk
+    return (const void *)k_pool<OP, FMT, 8>;
+  } else {
+    switch (kc) {
+      case 4: return (const void *)k_pool<OP, FMT, 4>;
+      case 16: return (const void *)k_pool<OP, FMT, 16>;
+      default: return (const void *)k_pool<OP, FMT, 8>;
+    }
+  }
+}
+
+static const void *pool_kernel(int op, int fmt, int kc) {
+  if (op == SLF_OP_SWEEP) {
+    switch (fmt) {
+      case SLF_FMT_U8: return pool_kernel<SLF_OP_SWEEP, SLF_FMT_U8>(kc);
+      case SLF_FMT_F16: return pool_kernel<SLF_OP_SWEEP, SLF_FMT_F16>(kc);
+      default: return pool_kernel<SLF_OP_SWEEP, SLF_FMT_F32>(kc);
+    }
+  }
+  switch (fmt) {
+    case SLF_FMT_U8: return pool_kernel<SLF_OP_REFINE, SLF_FMT_U8>(kc);
+    case SLF_FMT_F16: return pool_kernel<SLF_OP_REFINE, SLF_FMT_F16>(kc);
+    default: return pool_kernel<SLF_OP_REFINE, SLF_FMT_F32>(kc);
+  }
+}
+
+int pool_occupancy(int op, int fmt, int kc) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, pool_kernel(op, fmt, kc), kBlock, 0) != hipSuccess) return 0;
+  return n;
+}
+
+hipError_t launch_pool(int op, int fmt, int kc, const PoolStage *stage, int *counters, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_pool_reset, dim3(1), dim3(64), 0, st, counters);
+  void *args[] = {(void *)&stage, (void *)&counters};
+  const hipError_t e = hipLaunchKernel(pool_kernel(op, fmt, kc), dim3(blocks), dim3(kBlock), args, 0, st);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ warm start
+// Each grid cell keeps its 3D plane from the previous frame: the stored
+// inverse-depth row g (1/D(p) = g . p~) is unchanged, and the depth at the
+// new centroid is 1 / (g . c~).  A cell that was empty before, or whose plane
+// no longer faces the camera at its new centroid, starts fronto-parallel at
+// depth d_fb.
+__global__ void k_warm(const ViewDev *__restrict__ views, const int *__restrict__ sp_view,
+                       const int *__restrict__ area, const double2 *__restrict__ cen,
+                       const float4 *__restrict__ colour, float4 *planes, float4 *tab, int S, double d_fb) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= S) return;
+  const float4 C = colour[g];
+  if (area[g] == 0) {
+    planes[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+    tab[2 * g] = C;
+    tab[2 * g + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const float4 P = planes[g];
+  const float4 G = tab[2 * g + 1];
+  const double2 c = cen[g];
+  const double inv = (double)G.x * c.x + (double)G.y * c.y + (double)G.z;
+  float4 outP, outG;
+  if (P.x > 0.f && inv > 0.0) {
+    outP = make_float4((float)(1.0 / inv), P.y, P.z, P.w);
+    outG = G;
+  } else {
+    const ViewDev &vw = views[sp_view[g]];
+    outP = make_float4((float)d_fb, 0.f, 0.f, 1.f);
+    outG = make_float4((float)(vw.Kinv_d[6] / d_fb), (float)(vw.Kinv_d[7] / d_fb), (float)(vw.Kinv_d[8] / d_fb), 0.f);
+  }
+  planes[g] = outP;
+  tab[2 * g] = C;
+  tab[2 * g + 1] = outG;
+}
+
+hipError_t launch_warm(const ViewDev *views, const int *sp_view, const int *area, const double2 *cen,
+                       const float4 *colour, float4 *planes, float4 *tab, int S, double d_fb, hipStream_t st) {
+  hipLaunchKernelGGL(k_warm, dim3((S + 255) / 256), dim3(256), 0, st, views, sp_view, area, cen, colour, planes, tab,
+                     S, d_fb);
   return hipGetLastError();
 }
 

@@ -24,8 +24,12 @@ EXPORTED = [
     "slf_default_params", "slf_create", "slf_destroy", "slf_set_stream", "slf_set_params", "slf_set_cameras",
     "slf_set_neighbors", "slf_set_image_rgb8", "slf_set_labels", "slf_prepare", "slf_sweep", "slf_set_planes", "slf_propagate",
     "slf_get_planes", "slf_get_depth", "slf_get_superpixels", "slf_get_work", "slf_reset_work", "slf_synchronize",
-    "slf_status_string", "slf_last_error",
+    "slf_status_string", "slf_last_error", "slf_warm_start", "slf_get_footprint",
+    "slf_pool_default_config", "slf_pool_create", "slf_pool_destroy", "slf_pool_set_stream", "slf_pool_set_config",
+    "slf_pool_get_config", "slf_pool_attach", "slf_pool_detach", "slf_pool_usage", "slf_pool_submit", "slf_pool_step",
+    "slf_pool_run", "slf_pool_poll", "slf_pool_synchronize", "slf_pool_autotune", "slf_pool_last_error",
 ]
+SLF_POOL_SOLVE, SLF_POOL_PROPAGATE = 0, 1
 
 
 class slf_params(ctypes.Structure):
@@ -36,6 +40,15 @@ class slf_params(ctypes.Structure):
                 ("kernel_radius_init", ctypes.c_int32), ("term_mask", ctypes.c_uint32),
                 ("image_precision", ctypes.c_int32), ("homography_fp64", ctypes.c_int32),
                 ("energy_mode", ctypes.c_int32)]
+
+
+class slf_pool_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("sweep_level_chunk", ctypes.c_int32),
+                ("sweep_tile", ctypes.c_int32), ("refine_tile", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
 _lib = None
@@ -74,6 +87,27 @@ def load(path: str = LIB_PATH):
     L.slf_status_string.restype = ctypes.c_char_p
     L.slf_last_error.argtypes = [P]
     L.slf_last_error.restype = ctypes.c_char_p
+    U64, PU64, PI = ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int)
+    L.slf_warm_start.argtypes = [P]
+    L.slf_get_footprint.argtypes = [P, PU64]
+    L.slf_pool_default_config.argtypes = [ctypes.POINTER(slf_pool_config)]
+    L.slf_pool_default_config.restype = None
+    L.slf_pool_create.argtypes = [I, U64, ctypes.POINTER(P)]
+    L.slf_pool_destroy.argtypes = [P]
+    L.slf_pool_set_stream.argtypes = [P, P]
+    L.slf_pool_set_config.argtypes = [P, ctypes.POINTER(slf_pool_config)]
+    L.slf_pool_get_config.argtypes = [P, ctypes.POINTER(slf_pool_config)]
+    L.slf_pool_attach.argtypes = [P, P]
+    L.slf_pool_detach.argtypes = [P, P]
+    L.slf_pool_usage.argtypes = [P, PU64, PU64, PI, PI]
+    L.slf_pool_submit.argtypes = [P, P, I, I, I, U64]
+    L.slf_pool_step.argtypes = [P, PI]
+    L.slf_pool_run.argtypes = [P]
+    L.slf_pool_poll.argtypes = [P, P, I, PI]
+    L.slf_pool_synchronize.argtypes = [P]
+    L.slf_pool_autotune.argtypes = [P, PI]
+    L.slf_pool_last_error.argtypes = [P]
+    L.slf_pool_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         getattr(L, name)  # every declared entry point must be exported
     _lib = L
@@ -127,9 +161,17 @@ class Context:
         self.device = device
         self.dims = []
         self.grids = []
+        self._pool = None
 
     def close(self):
         if getattr(self, "_h", None):
+            if self._pool is not None:
+                try:
+                    self._pool.detach(self)
+                except SlfError:  # stages not yet launched: finish them first
+                    self._pool.run()
+                    self._pool.synchronize()
+                    self._pool.detach(self)
             self._L.slf_destroy(self._h)
             self._h = None
 
@@ -248,8 +290,118 @@ class Context:
         self._check(self._L.slf_get_work(self._h, ctypes.byref(e), ctypes.byref(s)))
         return int(e.value), int(s.value)
 
+    def warm_start(self) -> None:
+        self._check(self._L.slf_warm_start(self._h))
+
+    def footprint(self) -> int:
+        b = ctypes.c_uint64()
+        self._check(self._L.slf_get_footprint(self._h, ctypes.byref(b)))
+        return int(b.value)
+
     def reset_work(self) -> None:
         self._check(self._L.slf_reset_work(self._h))
 
     def synchronize(self) -> None:
         self._check(self._L.slf_synchronize(self._h))
+
+
+def default_pool_config(**overrides) -> slf_pool_config:
+    c = slf_pool_config()
+    load().slf_pool_default_config(ctypes.byref(c))
+    for k, v in overrides.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+class Pool:
+    """A rig pool (slf_pool_*): admission against an HBM budget, pooled
+    persistent launches, graph replay and iteration-level batching."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._L = load()
+        h = ctypes.c_void_p()
+        rc = self._L.slf_pool_create(device, hbm_budget_bytes, ctypes.byref(h))
+        if rc != SLF_OK:
+            raise SlfError(rc, "slf_pool_create")
+        self._h = h
+        self.device = device
+        self._rigs = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for c in list(self._rigs):
+                c._pool = None
+            self._rigs = []
+            self._L.slf_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != SLF_OK:
+            raise SlfError(rc, self._L.slf_pool_last_error(self._h).decode())
+        return rc
+
+    def last_error(self) -> str:
+        return self._L.slf_pool_last_error(self._h).decode()
+
+    def set_stream(self, stream) -> None:
+        ptr = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream or 0)
+        self._check(self._L.slf_pool_set_stream(self._h, ctypes.c_void_p(ptr)))
+
+    def set_config(self, cfg: slf_pool_config) -> None:
+        self._check(self._L.slf_pool_set_config(self._h, ctypes.byref(cfg)))
+
+    def get_config(self) -> slf_pool_config:
+        c = slf_pool_config()
+        self._check(self._L.slf_pool_get_config(self._h, ctypes.byref(c)))
+        return c
+
+    def attach(self, ctx: Context) -> None:
+        self._check(self._L.slf_pool_attach(self._h, ctx._h))
+        ctx._pool = self
+        self._rigs.append(ctx)
+
+    def detach(self, ctx: Context) -> None:
+        self._check(self._L.slf_pool_detach(self._h, ctx._h))
+        ctx._pool = None
+        self._rigs.remove(ctx)
+
+    def usage(self):
+        b, u = ctypes.c_uint64(), ctypes.c_uint64()
+        nr, na = ctypes.c_int(), ctypes.c_int()
+        self._check(self._L.slf_pool_usage(self._h, ctypes.byref(b), ctypes.byref(u), ctypes.byref(nr),
+                                           ctypes.byref(na)))
+        return {"budget": int(b.value), "used": int(u.value), "rigs": nr.value, "active": na.value}
+
+    def submit(self, ctx: Context, op: int, first_iter: int, n_iters: int, tag: int) -> None:
+        self._check(self._L.slf_pool_submit(self._h, ctx._h, op, first_iter, n_iters, tag))
+
+    def step(self) -> int:
+        n = ctypes.c_int()
+        self._check(self._L.slf_pool_step(self._h, ctypes.byref(n)))
+        return n.value
+
+    def run(self) -> None:
+        self._check(self._L.slf_pool_run(self._h))
+
+    def poll(self, max_tags: int = 256):
+        tags = np.zeros(max_tags, np.uint64)
+        n = ctypes.c_int()
+        self._check(self._L.slf_pool_poll(self._h, _ptr(tags), max_tags, ctypes.byref(n)))
+        return [int(t) for t in tags[:n.value]]
+
+    def synchronize(self) -> None:
+        self._check(self._L.slf_pool_synchronize(self._h))
+
+    def autotune(self) -> bool:
+        """Returns True when the configuration came from the pool's cache."""
+        hit = ctypes.c_int()
+        self._check(self._L.slf_pool_autotune(self._h, ctypes.byref(hit)))
+        return bool(hit.value)

@@ -107,3 +107,33 @@ def test_fullsize_pipeline_properties(full):
     assert ev > ev0 and sm > sm0
     D = ctx.get_depth(0)
     assert D.shape == (1080, 1920) and np.all(D > 0)
+
+
+def test_fullsize_end_to_end_depth_vs_oracle(full):
+    """The whole path (the sweep and all 8 iterations) against the oracle's own
+    end-to-end result on the same inputs, stored by
+    tests/golden/make_oracle_states.py (oracle only) and read out to depth by
+    the oracle.  Near-tie choices may legitimately differ and then propagate,
+    so the bar is on the distribution of per-pixel depth differences."""
+    import os
+
+    w, ctx, orc = full
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_state_fullhd.npz"))
+    assert str(ref["workload"]) == w.name and int(ref["iterations"]) == w.params.iterations
+    planes_o = ref["planes"].astype(np.float64)
+    _say("full-size end to end")
+    ctx.sweep()
+    ctx.propagate(1, w.params.iterations)
+    rel = []
+    for v in range(orc.V):
+        D_g = ctx.get_depth(v).astype(np.float64)
+        D_o = orc.render_depth(planes_o[orc.view_slice(v)], v)
+        m = (D_o > 0) & (D_g > 0)
+        assert m.mean() > 0.99
+        rel.append(np.abs(D_g[m] - D_o[m]) / D_o[m])
+    rel = np.concatenate(rel)
+    within = float((rel <= parity.DEPTH_REL).mean())
+    _say("end-to-end depth vs oracle: MARE %.4g, median %.3g, p90 %.3g, p99 %.3g, within 0.5%%: %.4f"
+         % (rel.mean(), np.median(rel), np.percentile(rel, 90), np.percentile(rel, 99), within))
+    assert np.median(rel) <= 1e-4
+    assert within >= 0.90
