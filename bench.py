@@ -28,8 +28,10 @@ sys.path.insert(0, ROOT)
 # minimum the method itself needs per sample.
 OPS_PER_SAMPLE_SWEEP = 35.0
 OPS_PER_SAMPLE_REFINE = 55.0
-# Non-packed FP32 VALU lane-ops/s of MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz.
-PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9
+# FP32 VALU lane-ops/s of MI355X (FMA = 1 op): 256 CUs x 128 FP32 lanes per
+# clock x 2.4 GHz = 78.6e12, i.e. the published 157.3 TFLOP/s FP32 vector peak
+# with an FMA counted as 2 flops.
+PEAK_VALU_OPS = 256 * 128 * 2.4e9
 
 
 def hbm_traffic(kernel):
@@ -209,7 +211,7 @@ def main():
     ctx.synchronize()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    evals, samples = ctx.work()
+    evals, samples, pruned = ctx.work_detail()
     K = args.steps
 
     def span(a, b):
@@ -257,6 +259,7 @@ def main():
         "ms_per_view": dt / K * 1e3 / V,
         "px_view_samples_per_s": samples / dt,
         "evals_per_step": evals // K,
+        "refine_candidates_pruned_per_step": pruned // K,
         "stage_ms": {"setup": float(np.mean(t_setup)), "sweep": sweep_ms, "refine_total": ref_ms,
                      "refine_per_iteration": [float(np.mean(t)) for t in t_ref]},
         "roofline": {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": peak,

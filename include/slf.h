@@ -162,10 +162,15 @@ int slf_get_depth(slf_ctx *ctx, int view, float *out, int64_t row_stride_elems, 
  * [K] int32, centroid [K][2] (u, v), mean colour [K][3] in [0,1]; NULL skips
  * an output.  Synchronises. */
 int slf_get_superpixels(slf_ctx *ctx, int view, int32_t *area, float *centroid, float *colour);
-/* Work done since the last reset: SP-plane hypothesis evaluations (one
- * (view, superpixel, plane) score) and px-view samples (one pixel tested in
- * one neighbour view under one plane).  Synchronises. */
-int slf_get_work(slf_ctx *ctx, uint64_t *evals, uint64_t *samples);
+/* Work done since the last reset; any output may be NULL.  evals: SP-plane
+ * hypotheses decided (one (view, superpixel, plane) score: a sweep level or
+ * a refinement candidate).  samples: px-view samples computed (one pixel
+ * tested in one neighbour view under one plane).  pruned: refinement
+ * candidates decided without their consistency term, because their
+ * smoothness times the consistency term's upper bound lay below the
+ * second-best energy so far (they can change neither the winner nor the
+ * margin; counted in evals, their samples are not taken).  Synchronises. */
+int slf_get_work(slf_ctx *ctx, uint64_t *evals, uint64_t *samples, uint64_t *pruned);
 int slf_reset_work(slf_ctx *ctx);
 /* Waits for all work enqueued by the context. */
 int slf_synchronize(slf_ctx *ctx);

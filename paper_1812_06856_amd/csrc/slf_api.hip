@@ -462,8 +462,8 @@ int slf_create(int device_ordinal, slf_ctx **out) {
     return SLF_EDEVICE;
   }
   if (hipMalloc((void **)&c->d_err, sizeof(int)) != hipSuccess ||
-      hipMalloc((void **)&c->d_work, 2 * sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->d_work, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+      hipMalloc((void **)&c->d_work, 3 * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_work, 0, 3 * sizeof(unsigned long long)) != hipSuccess) {
     free_all(c);
     delete c;
     return SLF_ENOMEM;
@@ -810,15 +810,16 @@ int slf_get_superpixels(slf_ctx *c, int view, int32_t *area, float *centroid, fl
   return SLF_OK;
 }
 
-int slf_get_work(slf_ctx *c, uint64_t *evals, uint64_t *samples) {
+int slf_get_work(slf_ctx *c, uint64_t *evals, uint64_t *samples, uint64_t *pruned) {
   if (!c) return SLF_EINVAL;
   if (int rc = check_idle(c)) return rc;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
-  unsigned long long w[2] = {0, 0};
+  unsigned long long w[3] = {0, 0, 0};
   HIP_OR_FAIL(c, hipMemcpyAsync(w, c->d_work, sizeof w, hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   if (evals) *evals = c->host_evals + w[0];
   if (samples) *samples = c->host_samples + w[1];
+  if (pruned) *pruned = w[2];
   return SLF_OK;
 }
 
@@ -826,7 +827,7 @@ int slf_reset_work(slf_ctx *c) {
   if (!c) return SLF_EINVAL;
   if (int rc = check_idle(c)) return rc;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
-  HIP_OR_FAIL(c, hipMemsetAsync(c->d_work, 0, 2 * sizeof(unsigned long long), c->stream));
+  HIP_OR_FAIL(c, hipMemsetAsync(c->d_work, 0, 3 * sizeof(unsigned long long), c->stream));
   c->host_evals = c->host_samples = 0;
   return SLF_OK;
 }

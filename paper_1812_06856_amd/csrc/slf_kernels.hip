@@ -647,7 +647,7 @@ __device__ __forceinline__ float3 load_f3(__amdgpu_buffer_rsrc_t rs, int off) {
 struct Best {
   float E, second;
   double d, nx, ny, nz, delta;
-  int slot, evaluated;
+  int slot, evaluated, pruned;
 };
 
 // Per-superpixel data the energy needs, uniform over the wave except the
@@ -677,9 +677,15 @@ __device__ __forceinline__ double bcast_d(double x, int l) {
 }
 
 // Energy E = E_c E_s (eqs. 3-11) of the 3D plane n . X = delta in camera r.
+// `e_floor` is the second-best energy so far: E_c <= 1 + occ (every S_i, V_i
+// and Gaussian mean is at most 1), so when E_s (1 + occ) lies below it, with
+// a margin far above FP32 rounding, the candidate can change neither the
+// winner nor the margin; then *pruned is set and the consistency loop is
+// skipped (results are unchanged).
 template <int FMT>
 __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, double nx, double ny, double nz,
-                        double delta) {
+                        double delta, float e_floor, bool &pruned) {
+  pruned = false;
   const int lane = threadIdx.x & (kWave - 1);
 
   if (a.energy_mode == 1) {  // data-only: -normalised TSSD of this plane
@@ -725,6 +731,13 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
     Es = ring_sum(num) / ring_sum(den);
   }
 
+  const float occ = (a.term_mask & 4u) ? a.eta * (1.f - c.omega_min) : 0.f;
+  const float ec_max = (a.term_mask & 2u) ? (1.f + occ) * 1.001f : 1.f;
+  if (Es * ec_max < e_floor) {
+    pruned = true;
+    return 0.f;
+  }
+
   // Consistency, eqs. (8)-(11).  Pixels are taken relative to the rounded
   // centroid (ub, vb) and projections relative to the integer pixel (X0, Y0)
   // nearest to the projected centroid, so the FP32 per-sample arithmetic
@@ -741,7 +754,6 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
     const float i0 = (float)(gd0 * c.ub + gd1 * c.vb + gd2);  // 1 / D at the rounded centroid
     const float gu = (float)gd0, gv = (float)gd1;
     float sum = 0.f;
-    const float occ = (a.term_mask & 4u) ? a.eta * (1.f - c.omega_min) : 0.f;
     const float tol = 1.f + a.occ_tol;
     for (int base = 0; base < c.N; base += kWave) {
       // lane j: constants of neighbour view base + j
@@ -912,8 +924,13 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
     cd.delta = uni_d(cd.delta);
     cd.d = uni_d(cd.d);
     cd.slot = __builtin_amdgcn_readfirstlane(cd.slot);
-    const float E = energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta);
+    bool pruned;
+    const float E = energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta, b.second, pruned);
     ++b.evaluated;
+    if (pruned) {  // bounded below the second best: no change
+      ++b.pruned;
+      continue;
+    }
     if (b.slot < 0 || E > b.E) {
       if (b.slot >= 0) b.second = b.E;
       b.E = E;
@@ -997,6 +1014,7 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
   b.second = -INFINITY;
   b.slot = -1;
   b.evaluated = 0;
+  b.pruned = 0;
   b.d = b.nx = b.ny = b.nz = b.delta = 0.0;
 
   // Propagation (Sec. III-C, eq. 4): slot r = 0 the current plane, 1 + j ring
@@ -1111,7 +1129,8 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
       a.margin[g] = b.evaluated > 1 ? b.E - b.second : INFINITY;
     }
     atomicAdd(&a.work[0], (unsigned long long)b.evaluated);
-    atomicAdd(&a.work[1], (unsigned long long)b.evaluated * (unsigned long long)c.A * (unsigned long long)c.N);
+    atomicAdd(&a.work[1], (unsigned long long)(b.evaluated - b.pruned) * (unsigned long long)c.A * (unsigned long long)c.N);
+    atomicAdd(&a.work[2], (unsigned long long)b.pruned);
   }
 }
 

@@ -585,11 +585,11 @@ int slf_pool_autotune(slf_pool *P, int *from_cache) {
     return SLF_OK;
   }
   // work counters and plane state are restored at the end
-  std::vector<unsigned long long> work(2 * P->rigs.size());
+  std::vector<unsigned long long> work(3 * P->rigs.size());
   std::vector<uint64_t> hwork(2 * P->rigs.size());
   for (size_t i = 0; i < P->rigs.size(); ++i) {
     slf_ctx *c = P->rigs[i];
-    if (hipMemcpy(&work[2 * i], c->d_work, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(&work[3 * i], c->d_work, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess)
       return P->fail(SLF_EDEVICE, "work counter read failed");
     hwork[2 * i] = c->host_evals;
     hwork[2 * i + 1] = c->host_samples;
@@ -635,7 +635,7 @@ int slf_pool_autotune(slf_pool *P, int *from_cache) {
   if (hipStreamSynchronize(P->stream) != hipSuccess) return P->fail(SLF_EDEVICE, "hipStreamSynchronize failed");
   for (size_t i = 0; i < P->rigs.size(); ++i) {
     slf_ctx *c = P->rigs[i];
-    if (hipMemcpy(c->d_work, &work[2 * i], 2 * sizeof(unsigned long long), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(c->d_work, &work[3 * i], 3 * sizeof(unsigned long long), hipMemcpyHostToDevice) != hipSuccess)
       return P->fail(SLF_EDEVICE, "work counter restore failed");
     for (auto &v : c->vh) v.has_planes = true;
     c->host_evals = hwork[2 * i];

@@ -80,7 +80,8 @@ def load(path: str = LIB_PATH):
     L.slf_get_planes.argtypes = [P, I, P, P, P, P]
     L.slf_get_depth.argtypes = [P, I, P, I64, I]
     L.slf_get_superpixels.argtypes = [P, I, P, P, P]
-    L.slf_get_work.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+    L.slf_get_work.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                               ctypes.POINTER(ctypes.c_uint64)]
     L.slf_reset_work.argtypes = [P]
     L.slf_synchronize.argtypes = [P]
     L.slf_status_string.argtypes = [I]
@@ -286,9 +287,14 @@ class Context:
         return area, cen, col
 
     def work(self):
-        e, s = ctypes.c_uint64(), ctypes.c_uint64()
-        self._check(self._L.slf_get_work(self._h, ctypes.byref(e), ctypes.byref(s)))
-        return int(e.value), int(s.value)
+        """(hypotheses decided, px-view samples computed)."""
+        return self.work_detail()[:2]
+
+    def work_detail(self):
+        """(hypotheses decided, px-view samples computed, refinement candidates pruned)."""
+        e, s, pr = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self._L.slf_get_work(self._h, ctypes.byref(e), ctypes.byref(s), ctypes.byref(pr)))
+        return int(e.value), int(s.value), int(pr.value)
 
     def warm_start(self) -> None:
         self._check(self._L.slf_warm_start(self._h))
