@@ -257,6 +257,10 @@ int slf::ensure_setup(slf_ctx *c) {
     int64_t texels = 0;
     for (const auto &v : c->vh) texels += (int64_t)v.W * v.H;
     const size_t need = (size_t)texels * quad_bytes(fmt);
+    // one 32-bit buffer resource covers every view's texels
+    if (need > 0xFFFFFFF0ull)
+      return c->fail(SLF_EUNSUPPORTED, "texel storage of %zu bytes exceeds 4 GiB; use a smaller image precision",
+                     need);
     if (need > c->quads_bytes) {
       if (c->d_quads) (void)hipFree(c->d_quads);
       c->d_quads = nullptr;
@@ -336,6 +340,7 @@ void slf::sweep_args(const slf_ctx *c, SweepArgs &a) {
   a.px_off = c->d_px_off;
   a.px = c->d_px;
   a.quads = c->d_quads;
+  a.quad_bytes = (uint32_t)c->quads_bytes;
   a.S = c->S;
   a.levels = c->p.levels;
   a.qmin = 1.0 / c->p.d_max;
@@ -378,6 +383,7 @@ void slf::refine_args(const slf_ctx *c, int iter, RefineArgs &a) {
   a.colour = c->d_colour;
   a.labels = c->d_labels;
   a.quads = c->d_quads;
+  a.quad_bytes = (uint32_t)c->quads_bytes;
   a.energy = c->d_energy;
   a.choice = c->d_choice;
   a.margin = c->d_margin;

@@ -53,6 +53,7 @@ struct SweepArgs {
   const int *px_off;
   const PixEntry *px;
   const void *quads;
+  uint32_t quad_bytes;  // bytes of texels over all views (< 4 GiB)
   int S;
   int levels;
   double qmin, dq;     // inverse-depth range start and bin width
@@ -78,6 +79,7 @@ struct RefineArgs {
   const float4 *colour;   // mean colour in [0,1]
   const int *labels;      // all views
   const void *quads;      // images (data-only energy mode)
+  uint32_t quad_bytes;    // bytes of texels over all views (< 4 GiB)
   const float4 *planesA;  // state read
   const float4 *tabA;     // per superpixel {colour, inverse-depth row} of state A
   float4 *planesB;        // state written

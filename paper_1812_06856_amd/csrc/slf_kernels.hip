@@ -127,12 +127,24 @@ size_t quad_bytes(int fmt) { return fmt == SLF_FMT_F32 ? 64 : fmt == SLF_FMT_F16
 template <int FMT>
 constexpr int kQuadBytes = FMT == SLF_FMT_F32 ? 64 : FMT == SLF_FMT_F16 ? 32 : 16;
 
+// Raw buffer resource over `bytes` bytes at p (gfx9-family descriptor word 3):
+// loads past the end return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ uint4 load_u4(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+}
+
+// The four bilinear taps of the texel at byte offset off (a 2x2 footprint)
+// as 4 x RGB floats, read through a buffer resource over all texels.
 template <int FMT>
-__device__ __forceinline__ void fetch_quad(const void *base, int64_t idx, float (&t)[12]);
+__device__ __forceinline__ void fetch_quad(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&t)[12]);
 
 template <>
-__device__ __forceinline__ void fetch_quad<SLF_FMT_U8>(const void *base, int64_t idx, float (&t)[12]) {
-  const uint4 q = static_cast<const uint4 *>(base)[idx];
+__device__ __forceinline__ void fetch_quad<SLF_FMT_U8>(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&t)[12]) {
+  const uint4 q = load_u4(rs, off);
   const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -143,9 +155,8 @@ __device__ __forceinline__ void fetch_quad<SLF_FMT_U8>(const void *base, int64_t
 }
 
 template <>
-__device__ __forceinline__ void fetch_quad<SLF_FMT_F16>(const void *base, int64_t idx, float (&t)[12]) {
-  const uint4 *p = static_cast<const uint4 *>(base) + 2 * idx;
-  const uint4 a = p[0], b = p[1];
+__device__ __forceinline__ void fetch_quad<SLF_FMT_F16>(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&t)[12]) {
+  const uint4 a = load_u4(rs, off), b = load_u4(rs, off + 16u);
   const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -158,11 +169,10 @@ __device__ __forceinline__ void fetch_quad<SLF_FMT_F16>(const void *base, int64_
 }
 
 template <>
-__device__ __forceinline__ void fetch_quad<SLF_FMT_F32>(const void *base, int64_t idx, float (&t)[12]) {
-  const float4 *p = static_cast<const float4 *>(base) + 4 * idx;
+__device__ __forceinline__ void fetch_quad<SLF_FMT_F32>(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&t)[12]) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const float4 c = p[j];
+    const float4 c = __builtin_bit_cast(float4, load_u4(rs, off + 16u * j));
     t[3 * j + 0] = c.x;
     t[3 * j + 1] = c.y;
     t[3 * j + 2] = c.z;
@@ -405,7 +415,8 @@ hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V
 // always in bounds and issued unconditionally.
 template <int FMT>
 __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm1, float Hm1, int Wi, int Hi,
-                                             const void *quads, float r0, float g0, float b0, float T) {
+                                             __amdgpu_buffer_rsrc_t quads, uint32_t vbase, float r0, float g0,
+                                             float b0, float T) {
   const float rw = rcp(w);
   const float xs = x * rw, ys = y * rw;
   // Clamp into the image; the sample counts only if unclamped (a NaN fails
@@ -417,7 +428,7 @@ __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm
   const int x0 = (int)xc, y0 = (int)yc;
   const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
   float t[12];
-  fetch_quad<FMT>(quads, (int64_t)(y0 * Wi + x0), t);
+  fetch_quad<FMT>(quads, vbase + (uint32_t)(y0 * Wi + x0) * (uint32_t)kQuadBytes<FMT>, t);
   // bilinear weights of the four taps (FP16 taps feed mixed-precision FMAs directly)
   const float ofx = 1.f - fx, ofy = 1.f - fy;
   const float w00 = ofx * ofy, w10 = fx * ofy, w01 = ofx * fy, w11 = fx * fy;
@@ -436,16 +447,16 @@ __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm
 // rounding (<= 0.125 grey levels).
 template <>
 __device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, float w, float Wm1, float Hm1, int Wi,
-                                                          int Hi, const void *quads, float r0, float g0, float b0,
-                                                          float T) {
+                                                          int Hi, __amdgpu_buffer_rsrc_t quads, uint32_t vbase,
+                                                          float r0, float g0, float b0, float T) {
   const float rw = rcp(w);
   const float xs = x * rw, ys = y * rw;
   const float xc = __builtin_amdgcn_fmed3f(xs, 0.f, Wm1), yc = __builtin_amdgcn_fmed3f(ys, 0.f, Hm1);
   const bool in = (w > 0.f) & (xc == xs) & (yc == ys);
   const int x0 = (int)xc, y0 = (int)yc;
   const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
-  const uint4 *q = static_cast<const uint4 *>(quads) + 2 * (int64_t)(y0 * Wi + x0);
-  const uint4 lo = q[0], hi = q[1];
+  const uint32_t off = vbase + (uint32_t)(y0 * Wi + x0) * 32u;
+  const uint4 lo = load_u4(quads, off), hi = load_u4(quads, off + 16u);
   const float ofx = 1.f - fx, ofy = 1.f - fy;
   const __half2 w00 = __float2half2_rn(ofx * ofy), w10 = __float2half2_rn(fx * ofy);
   const __half2 w01 = __float2half2_rn(ofx * fy), w11 = __float2half2_rn(fx * fy);
@@ -466,9 +477,11 @@ __device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, floa
   return in ? fminf(ssd, T) : T;
 }
 
-// Address of view i's texels.
-__device__ __forceinline__ const void *quad_base(const void *quads, int fmt_bytes, int64_t quad_off) {
-  return static_cast<const char *>(quads) + quad_off * fmt_bytes;
+// Byte offset of view i's texels in the texel array (which the host keeps
+// under 4 GiB, so that one wave-uniform buffer resource covers every view).
+template <int FMT>
+__device__ __forceinline__ uint32_t quad_base(const ViewDev &vi) {
+  return (uint32_t)vi.quad_off * (uint32_t)kQuadBytes<FMT>;
 }
 
 #ifndef SLF_XCD_REMAP
@@ -543,7 +556,8 @@ __device__ __forceinline__ void sweep_sp(const SweepArgs &a, const int g) {
     float A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, A5 = 0, A6 = 0, A7 = 0, A8 = 0, bx = 0, by = 0, bw = 0;
     float Wm1 = 0, Hm1 = 0;
     int Wi = 2, Hi = 2;
-    const void *qbase = a.quads;
+    const __amdgpu_buffer_rsrc_t qrs = buffer_rsrc(a.quads, a.quad_bytes);
+    uint32_t qbase = 0;
     for (int j = lane; j < P; j += kWave) {
       if (iv != cur) {
         const PairDev &pg = a.pairs[vw.pair_off + iv];
@@ -556,7 +570,7 @@ __device__ __forceinline__ void sweep_sp(const SweepArgs &a, const int g) {
         Hi = vi.H;
         Wm1 = (float)(Wi - 1);
         Hm1 = (float)(Hi - 1);
-        qbase = quad_base(a.quads, kQuadBytes<FMT>, vi.quad_off);
+        qbase = quad_base<FMT>(vi);
         cur = iv;
       }
       const PixEntry e = a.px[poff + p];
@@ -568,7 +582,7 @@ __device__ __forceinline__ void sweep_sp(const SweepArgs &a, const int g) {
 #pragma unroll
       for (int kk = 0; kk < KC; ++kk) {
         acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi,
-                                    Hi, qbase, r0, g0, b0, a.T255);
+                                    Hi, qrs, qbase, r0, g0, b0, a.T255);
       }
       p += kWave;
       while (p >= A) {
@@ -633,11 +647,6 @@ constexpr int kLdsPix = 1024;  // pixels of a superpixel staged in LDS (the rest
 
 typedef __attribute__((address_space(3))) uint32_t LdsU32;
 
-// Raw buffer resource over `bytes` bytes at p (gfx9-family descriptor word 3):
-// loads past the end return 0.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
 __device__ __forceinline__ float3 load_f3(__amdgpu_buffer_rsrc_t rs, int off) {
   typedef float f3v __attribute__((ext_vector_type(3)));
   const f3v v = __builtin_bit_cast(f3v, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0));
@@ -707,7 +716,7 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         const float pu = (float)(e.x & 0xffffu), pv = (float)(e.x >> 16);
         acc += tssd_sample<FMT>(fmaf(H[0], pu, fmaf(H[1], pv, H[2])), fmaf(H[3], pu, fmaf(H[4], pv, H[5])),
                                 fmaf(H[6], pu, fmaf(H[7], pv, H[8])), (float)(vi.W - 1), (float)(vi.H - 1), vi.W,
-                                vi.H, quad_base(a.quads, kQuadBytes<FMT>, vi.quad_off), (float)(e.y & 255u),
+                                vi.H, buffer_rsrc(a.quads, a.quad_bytes), quad_base<FMT>(vi), (float)(e.y & 255u),
                                 (float)((e.y >> 8) & 255u), (float)((e.y >> 16) & 255u), a.T255);
       }
     }
