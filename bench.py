@@ -34,6 +34,10 @@ OPS_PER_SAMPLE_REFINE = 55.0
 PEAK_VALU_OPS = 256 * 128 * 2.4e9
 
 
+def _progress(msg):
+    print("[bench %s] %s" % (time.strftime("%H:%M:%S"), msg), file=sys.stderr, flush=True)
+
+
 def hbm_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, calibrated by a plain device copy), or
@@ -329,6 +333,7 @@ def run_precision(args):
 
     forms = {}
     for name, fmt in [("f32", slf.SLF_IMAGE_F32), ("f16", slf.SLF_IMAGE_F16), ("u8", slf.SLF_IMAGE_U8)]:
+        _progress("precision form %s" % name)
         ctx = slf.Context(0)
         ctx.set_stream(stream)
         imgs, labs, depth = _load_rig_inputs(ctx, w, dev, stream, fmt)
@@ -414,7 +419,10 @@ def run_batched(args):
     from paper_1812_06856_amd import slf
 
     t_gen = time.perf_counter()
-    ws = [configs.rig_batched(j) for j in range(args.rigs)]
+    ws = []
+    for j in range(args.rigs):
+        ws.append(configs.rig_batched(j))
+        _progress("generated %s" % ws[-1].rig.name)
     t_gen = time.perf_counter() - t_gen
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
@@ -443,9 +451,11 @@ def run_batched(args):
     for c in ctxs:
         pool.attach(c)
     load_and_prepare()
+    _progress("autotuning")
     t_tune = time.perf_counter()
     pool.autotune()
     t_tune = time.perf_counter() - t_tune
+    _progress("autotuned in %.1f s: %s" % (t_tune, pool.get_config().as_dict()))
     cfg = pool.get_config().as_dict()
 
     def ev():
@@ -481,6 +491,7 @@ def run_batched(args):
         pooled_step()
         solo_step()
     torch.cuda.synchronize()
+    _progress("warm-up done")
     for c in ctxs:
         c.reset_work()
     torch.cuda.synchronize()
@@ -536,7 +547,10 @@ def run_serving(args):
     t_gen = time.perf_counter()
     seqs = [configs.serving_rig(j) for j in range(args.serve_rigs)]
     F = args.serve_frames
-    frames = [[s.frame(k) for k in range(F)] for s in seqs]
+    frames = []
+    for s in seqs:
+        frames.append([s.frame(k) for k in range(F)])
+        _progress("rendered %d frames of %s" % (F, s.name))
     t_gen = time.perf_counter() - t_gen
     dev = torch.device("cuda:0")
     pool = slf.Pool(0)
@@ -575,7 +589,9 @@ def run_serving(args):
     tag = 0
     a = 0
     samples0 = sum(c.work()[1] for c in ctxs)
+    _progress("serving %d arrivals over %.0f s" % (len(arrivals), horizon))
     t0 = time.perf_counter()
+    next_report = 5.0
     while a < len(arrivals) or any(b is not None for b in busy) or reading or any(queue):
         now = time.perf_counter() - t0
         while a < len(arrivals) and arrivals[a][0] <= now:
@@ -617,6 +633,9 @@ def run_serving(args):
                 if arr >= args.serve_warmup_s:
                     latency.append((done - arr) * 1e3)
                 del reading[tg]
+        if now >= next_report:
+            _progress("t=%.0f s: %d arrived, %d measured" % (now, a, len(latency)))
+            next_report += 5.0
         if not pool.usage()["active"] and not reading:
             time.sleep(0.0002)
     wall = time.perf_counter() - t0
