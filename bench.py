@@ -324,7 +324,7 @@ def run_precision(args):
         ref = np.load(ref_path)
         orc = Oracle(w.rig, p)
         planes = ref["planes"].astype(np.float64)
-        orc_depth = [orc.render_depth(planes[orc.view_slice(v)], v) for v in range(V)]
+        orc_depth = [orc.render_depth(planes, v) for v in range(V)]
 
     def ev():
         e = torch.cuda.Event(enable_timing=True)

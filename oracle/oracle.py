@@ -282,7 +282,10 @@ class Oracle:
         return pl, e.value, ch.value, slots[:n], planes[:n], en[:n]
 
     def render_depth(self, planes, view):
+        """Depth map of `view` from the full plane state [S_total, 4] (all views)."""
         planes = np.ascontiguousarray(planes, np.float64)
+        if planes.shape != (self.S, 4):
+            raise ValueError("render_depth needs the state of every view, shape (%d, 4)" % self.S)
         W, H = self.dims[view]
         out = np.empty((H, W))
         self._L.slfo_render_depth(self._c, _p(planes), view, _p(out))
