@@ -448,9 +448,9 @@ def run_batched(args):
             for i in range(len(depth)):
                 c.get_depth(i, out=depth[i])
 
+    load_and_prepare()
     for c in ctxs:
         pool.attach(c)
-    load_and_prepare()
     _progress("autotuning")
     t_tune = time.perf_counter()
     pool.autotune()
@@ -564,6 +564,9 @@ def run_serving(args):
         with torch.cuda.stream(st):
             data.append([([torch.from_numpy(v.rgb).to(dev) for v in fr.views],
                           [torch.from_numpy(v.labels).to(dev) for v in fr.views]) for fr in frames[j]])
+        for i, v in enumerate(frames[j][0].views):  # frame 0 inputs: the label grids the footprint needs
+            c.set_image(i, data[j][0][0][i])
+            c.set_labels(i, data[j][0][1][i], v.gw, v.gh)
         streams.append(st)
         ctxs.append(c)
         depth.append(dep)

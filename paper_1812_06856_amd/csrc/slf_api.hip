@@ -164,7 +164,7 @@ int build_geometry(slf_ctx *c) {
     if ((int64_t)sp + K > (int64_t)1 << 30) return c->fail(SLF_EUNSUPPORTED, "too many superpixels");
     sp += (int)K;
     px += (int64_t)h.W * h.H;
-    qd += (int64_t)h.W * h.H;
+    qd += (int64_t)(h.W + 1) * (h.H + 1);
     // pairs: A = K_i R_ri K_r^-1, b = K_i t_ri, R_ri = R_i R_r^T, t_ri = t_i - R_ri t_r
     for (int i : h.nbrs) {
       const ViewHost &hi = c->vh[i];
@@ -255,7 +255,7 @@ int slf::ensure_setup(slf_ctx *c) {
   const int fmt = c->p.image_precision;
   if (c->quads_dirty || c->quads_fmt != fmt) {
     int64_t texels = 0;
-    for (const auto &v : c->vh) texels += (int64_t)v.W * v.H;
+    for (const auto &v : c->vh) texels += (int64_t)(v.W + 1) * (v.H + 1);
     const size_t need = (size_t)texels * quad_bytes(fmt);
     // one 32-bit buffer resource covers every view's texels
     if (need > 0xFFFFFFF0ull)
@@ -309,17 +309,18 @@ int slf::ensure_setup(slf_ctx *c) {
 
 int slf::footprint(const slf_ctx *c, uint64_t *bytes) {
   if (c->V < 2) return SLF_ESTATE;
-  uint64_t px = 0, S = 0, pairs = 0, max_px = 0;
+  uint64_t px = 0, S = 0, pairs = 0, max_px = 0, texels = 0;
   for (const auto &v : c->vh) {
     if (v.gw < 1 || v.gh < 1) return SLF_ESTATE;
     px += (uint64_t)v.W * v.H;
+    texels += (uint64_t)(v.W + 1) * (v.H + 1);
     max_px = std::max<uint64_t>(max_px, (uint64_t)v.W * v.H);
     S += (uint64_t)v.gw * v.gh;
     pairs += v.nbrs.size();
   }
   uint64_t b = 0;
   b += px * 3 + px * sizeof(int);                                 // images, labels
-  b += px * quad_bytes(c->p.image_precision);                     // bilinear texels
+  b += texels * quad_bytes(c->p.image_precision);                 // bilinear texels
   b += sizeof(ViewDev) * c->V + sizeof(PairDev) * pairs + 64;     // geometry, flags, counters
   b += S * (4 * sizeof(int) + sizeof(int4) + sizeof(float2) + sizeof(double2) + sizeof(float4));
   b += sizeof(int) * ((S + 4095) / 4096 + 2);                     // scan blocks, offsets

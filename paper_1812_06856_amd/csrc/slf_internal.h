@@ -23,7 +23,7 @@ struct ViewDev {
   int n_pairs;         // |N(r)|
   int kr_init;         // initial propagation kernel radius, grid cells
   int64_t pix_off;     // first pixel of this view in per-pixel arrays (labels, rgb)
-  int64_t quad_off;    // first texel of this view in the texel image (W x H texels)
+  int64_t quad_off;    // first texel of this view in the texel array ((W+1) x (H+1) texels)
   float Kinv[9];       // K^-1 rounded to FP32
   float pad1[3];
   double Kinv_d[9];    // K^-1 in FP64

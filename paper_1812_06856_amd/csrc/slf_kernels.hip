@@ -123,9 +123,11 @@ __device__ __forceinline__ float bcast(float x, int l) {
 // taps (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1), with the last column and
 // row replicated, so one aligned load fetches a whole bilinear footprint.
 
-size_t quad_bytes(int fmt) { return fmt == SLF_FMT_F32 ? 64 : fmt == SLF_FMT_F16 ? 32 : 16; }
+// Texels: per view a (W+1) x (H+1) RGBA image (last column and row
+// replicated), 4 / 8 / 16 bytes per texel for RGBA8 / FP16 / FP32.
+size_t quad_bytes(int fmt) { return fmt == SLF_FMT_F32 ? 16 : fmt == SLF_FMT_F16 ? 8 : 4; }
 template <int FMT>
-constexpr int kQuadBytes = FMT == SLF_FMT_F32 ? 64 : FMT == SLF_FMT_F16 ? 32 : 16;
+constexpr int kQuadBytes = FMT == SLF_FMT_F32 ? 16 : FMT == SLF_FMT_F16 ? 8 : 4;
 
 // Raw buffer resource over `bytes` bytes at p (gfx9-family descriptor word 3):
 // loads past the end return 0.
@@ -136,16 +138,21 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, uin
 __device__ __forceinline__ uint4 load_u4(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
 }
+__device__ __forceinline__ uint2 load_u2(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+}
 
-// The four bilinear taps of the texel at byte offset off (a 2x2 footprint)
-// as 4 x RGB floats, read through a buffer resource over all texels.
+// The four bilinear taps (x0, y0), (x0+1, y0), (x0, y0+1), (x0+1, y0+1) as
+// 4 x RGB floats: two loads of two adjacent texels, `off` the byte offset
+// of texel (x0, y0) and `row` the bytes of one texel row.
 template <int FMT>
-__device__ __forceinline__ void fetch_quad(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&t)[12]);
+__device__ __forceinline__ void fetch_quad(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t row, float (&t)[12]);
 
 template <>
-__device__ __forceinline__ void fetch_quad<SLF_FMT_U8>(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&t)[12]) {
-  const uint4 q = load_u4(rs, off);
-  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+__device__ __forceinline__ void fetch_quad<SLF_FMT_U8>(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t row,
+                                                       float (&t)[12]) {
+  const uint2 a = load_u2(rs, off), b = load_u2(rs, off + row);
+  const uint32_t w[4] = {a.x, a.y, b.x, b.y};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     t[3 * j + 0] = (float)(w[j] & 255u);
@@ -155,8 +162,9 @@ __device__ __forceinline__ void fetch_quad<SLF_FMT_U8>(__amdgpu_buffer_rsrc_t rs
 }
 
 template <>
-__device__ __forceinline__ void fetch_quad<SLF_FMT_F16>(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&t)[12]) {
-  const uint4 a = load_u4(rs, off), b = load_u4(rs, off + 16u);
+__device__ __forceinline__ void fetch_quad<SLF_FMT_F16>(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t row,
+                                                        float (&t)[12]) {
+  const uint4 a = load_u4(rs, off), b = load_u4(rs, off + row);
   const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -169,10 +177,12 @@ __device__ __forceinline__ void fetch_quad<SLF_FMT_F16>(__amdgpu_buffer_rsrc_t r
 }
 
 template <>
-__device__ __forceinline__ void fetch_quad<SLF_FMT_F32>(__amdgpu_buffer_rsrc_t rs, uint32_t off, float (&t)[12]) {
+__device__ __forceinline__ void fetch_quad<SLF_FMT_F32>(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t row,
+                                                        float (&t)[12]) {
+  const uint32_t o[4] = {off, off + 16u, off + row, off + row + 16u};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const float4 c = __builtin_bit_cast(float4, load_u4(rs, off + 16u * j));
+    const float4 c = __builtin_bit_cast(float4, load_u4(rs, o[j]));
     t[3 * j + 0] = c.x;
     t[3 * j + 1] = c.y;
     t[3 * j + 2] = c.z;
@@ -181,43 +191,27 @@ __device__ __forceinline__ void fetch_quad<SLF_FMT_F32>(__amdgpu_buffer_rsrc_t r
 
 __global__ __launch_bounds__(256) void k_quads(const uint8_t *rgb, int W, int H, void *quads, int64_t quad_off,
                                                int fmt) {
-  const int64_t n = (int64_t)W * H;
+  const int Wp = W + 1;
+  const int64_t n = (int64_t)Wp * (H + 1);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n) return;
-  const int x0 = (int)(idx % W), y0 = (int)(idx / W);
-  const int x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1);  // replicated edge: weight 0 there
-  const int64_t px[4] = {(int64_t)y0 * W + x0, (int64_t)y0 * W + x1, (int64_t)y1 * W + x0, (int64_t)y1 * W + x1};
+  const int x = min((int)(idx % Wp), W - 1), y = min((int)(idx / Wp), H - 1);  // replicated edge
+  const uint8_t *c = rgb + 3 * ((int64_t)y * W + x);
   if (fmt == SLF_FMT_U8) {
-    uint32_t w[4];
-    for (int j = 0; j < 4; ++j) {
-      const uint8_t *c = rgb + 3 * px[j];
-      w[j] = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
-    }
-    static_cast<uint4 *>(quads)[quad_off + idx] = make_uint4(w[0], w[1], w[2], w[3]);
+    static_cast<uint32_t *>(quads)[quad_off + idx] = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
   } else if (fmt == SLF_FMT_F16) {
-    uint32_t w[8];
-    for (int j = 0; j < 4; ++j) {
-      const uint8_t *c = rgb + 3 * px[j];
-      __half2 rg = __floats2half2_rn((float)c[0], (float)c[1]);
-      __half2 ba = __floats2half2_rn((float)c[2], 0.f);
-      w[2 * j] = *reinterpret_cast<uint32_t *>(&rg);
-      w[2 * j + 1] = *reinterpret_cast<uint32_t *>(&ba);
-    }
-    uint4 *out = static_cast<uint4 *>(quads) + 2 * (quad_off + idx);
-    out[0] = make_uint4(w[0], w[1], w[2], w[3]);
-    out[1] = make_uint4(w[4], w[5], w[6], w[7]);
+    __half2 rg = __floats2half2_rn((float)c[0], (float)c[1]);
+    __half2 ba = __floats2half2_rn((float)c[2], 0.f);
+    static_cast<uint2 *>(quads)[quad_off + idx] =
+        make_uint2(*reinterpret_cast<uint32_t *>(&rg), *reinterpret_cast<uint32_t *>(&ba));
   } else {
-    float4 *out = static_cast<float4 *>(quads) + 4 * (quad_off + idx);
-    for (int j = 0; j < 4; ++j) {
-      const uint8_t *c = rgb + 3 * px[j];
-      out[j] = make_float4((float)c[0], (float)c[1], (float)c[2], 0.f);
-    }
+    static_cast<float4 *>(quads)[quad_off + idx] = make_float4((float)c[0], (float)c[1], (float)c[2], 0.f);
   }
 }
 
 hipError_t launch_quads(int fmt, const uint8_t *rgb, int64_t, int W, int H, void *quads, int64_t quad_off,
                         hipStream_t st) {
-  const int64_t n = (int64_t)W * H;
+  const int64_t n = (int64_t)(W + 1) * (H + 1);
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_quads, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rgb, W, H, quads, quad_off, fmt);
   return hipGetLastError();
@@ -428,7 +422,8 @@ __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm
   const int x0 = (int)xc, y0 = (int)yc;
   const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
   float t[12];
-  fetch_quad<FMT>(quads, vbase + (uint32_t)(y0 * Wi + x0) * (uint32_t)kQuadBytes<FMT>, t);
+  const uint32_t row = (uint32_t)(Wi + 1) * (uint32_t)kQuadBytes<FMT>;
+  fetch_quad<FMT>(quads, vbase + (uint32_t)(y0 * (Wi + 1) + x0) * (uint32_t)kQuadBytes<FMT>, row, t);
   // bilinear weights of the four taps (FP16 taps feed mixed-precision FMAs directly)
   const float ofx = 1.f - fx, ofy = 1.f - fy;
   const float w00 = ofx * ofy, w10 = fx * ofy, w01 = ofx * fy, w11 = fx * fy;
@@ -437,43 +432,6 @@ __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm
   for (int c = 0; c < 3; ++c) b[c] = fmaf(w11, t[9 + c], fmaf(w01, t[6 + c], fmaf(w10, t[3 + c], w00 * t[c])));
   const float d0 = r0 - b[0], d1 = g0 - b[1], d2 = b0 - b[2];
   const float ssd = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
-  return in ? fminf(ssd, T) : T;
-}
-
-// Precision form: FP16 texels interpolated with packed FP16 FMAs (two
-// channels per instruction), the squared difference summed by a dot
-// product with FP32 accumulation, the cost accumulated in FP32.  Taps are
-// exact in FP16 (integers 0..255); the interpolated colour carries FP16
-// rounding (<= 0.125 grey levels).
-template <>
-__device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, float w, float Wm1, float Hm1, int Wi,
-                                                          int Hi, __amdgpu_buffer_rsrc_t quads, uint32_t vbase,
-                                                          float r0, float g0, float b0, float T) {
-  const float rw = rcp(w);
-  const float xs = x * rw, ys = y * rw;
-  const float xc = __builtin_amdgcn_fmed3f(xs, 0.f, Wm1), yc = __builtin_amdgcn_fmed3f(ys, 0.f, Hm1);
-  const bool in = (w > 0.f) & (xc == xs) & (yc == ys);
-  const int x0 = (int)xc, y0 = (int)yc;
-  const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
-  const uint32_t off = vbase + (uint32_t)(y0 * Wi + x0) * 32u;
-  const uint4 lo = load_u4(quads, off), hi = load_u4(quads, off + 16u);
-  const float ofx = 1.f - fx, ofy = 1.f - fy;
-  const __half2 w00 = __float2half2_rn(ofx * ofy), w10 = __float2half2_rn(fx * ofy);
-  const __half2 w01 = __float2half2_rn(ofx * fy), w11 = __float2half2_rn(fx * fy);
-  auto h2 = [](uint32_t u) { return *reinterpret_cast<const __half2 *>(&u); };
-  __half2 rg = __hmul2(w00, h2(lo.x));
-  rg = __hfma2(w10, h2(lo.z), rg);
-  rg = __hfma2(w01, h2(hi.x), rg);
-  rg = __hfma2(w11, h2(hi.z), rg);
-  __half2 bz = __hmul2(w00, h2(lo.y));
-  bz = __hfma2(w10, h2(lo.w), bz);
-  bz = __hfma2(w01, h2(hi.y), bz);
-  bz = __hfma2(w11, h2(hi.w), bz);
-  const __half2 drg = __hsub2(__floats2half2_rn(r0, g0), rg);
-  const __half2 db = __hsub2(__floats2half2_rn(b0, 0.f), bz);
-  typedef _Float16 hv2 __attribute__((ext_vector_type(2)));
-  const hv2 vrg = *reinterpret_cast<const hv2 *>(&drg), vb = *reinterpret_cast<const hv2 *>(&db);
-  const float ssd = __builtin_amdgcn_fdot2(vrg, vrg, __builtin_amdgcn_fdot2(vb, vb, 0.f, false), false);
   return in ? fminf(ssd, T) : T;
 }
 
