@@ -602,6 +602,10 @@ hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st) {
 
 
 constexpr int kLdsPix = 1024;  // pixels of a superpixel staged in LDS (the rest read from the list)
+#ifndef SLF_REFINE_CHAINS
+#define SLF_REFINE_CHAINS 2
+#endif
+constexpr int kChains = SLF_REFINE_CHAINS;  // independent gather chains per lane in the energy loop
 
 typedef __attribute__((address_space(3))) uint32_t LdsU32;
 
@@ -814,19 +818,27 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           const uint32_t l = label(q);
           accumulate(q, load_f3(tab_rs, (int)(32u * l)), load_f3(tab_rs, (int)(32u * l + 16u)));
         };
-        // Two pixels per lane per pass keep two gather chains in flight;
-        // each lane still accumulates its pixels in order.
+        // kChains pixels per lane per pass keep that many gather chains in
+        // flight; each lane still accumulates its pixels in order.
         const int n_lds = min(c.A, kLdsPix);
         int p = lane;
-        for (; p + kWave < n_lds; p += 2 * kWave) {
-          const Proj q0 = project(c.pix_lds[p]), q1 = project(c.pix_lds[p + kWave]);
-          const uint32_t l0 = label(q0), l1 = label(q1);
-          const float3 C0 = load_f3(tab_rs, (int)(32u * l0)), G0 = load_f3(tab_rs, (int)(32u * l0 + 16u));
-          const float3 C1 = load_f3(tab_rs, (int)(32u * l1)), G1 = load_f3(tab_rs, (int)(32u * l1 + 16u));
-          accumulate(q0, C0, G0);
-          accumulate(q1, C1, G1);
+        for (; p + (kChains - 1) * kWave < n_lds; p += kChains * kWave) {
+          Proj q[kChains];
+          uint32_t l[kChains];
+          float3 C[kChains], G[kChains];
+#pragma unroll
+          for (int k = 0; k < kChains; ++k) q[k] = project(c.pix_lds[p + k * kWave]);
+#pragma unroll
+          for (int k = 0; k < kChains; ++k) l[k] = label(q[k]);
+#pragma unroll
+          for (int k = 0; k < kChains; ++k) {
+            C[k] = load_f3(tab_rs, (int)(32u * l[k]));
+            G[k] = load_f3(tab_rs, (int)(32u * l[k] + 16u));
+          }
+#pragma unroll
+          for (int k = 0; k < kChains; ++k) accumulate(q[k], C[k], G[k]);
         }
-        if (p < n_lds) one(c.pix_lds[p]);
+        for (; p < n_lds; p += kWave) one(c.pix_lds[p]);
         for (p = kLdsPix + lane; p < c.A; p += kWave) one(a.px[c.poff + p].x);
         const float swt = wave_sum(sw);
         const float gxt = wave_sum(gx);
