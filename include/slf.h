@@ -166,10 +166,12 @@ int slf_get_superpixels(slf_ctx *ctx, int view, int32_t *area, float *centroid, 
  * hypotheses decided (one (view, superpixel, plane) score: a sweep level or
  * a refinement candidate).  samples: px-view samples computed (one pixel
  * tested in one neighbour view under one plane).  pruned: refinement
- * candidates decided without their consistency term, because their
- * smoothness times the consistency term's upper bound lay below the
- * second-best energy so far (they can change neither the winner nor the
- * margin; counted in evals, their samples are not taken).  Synchronises. */
+ * candidates decided before their consistency term was complete: after
+ * each neighbour view, the smoothness times an upper bound of the
+ * consistency term (views left contributing at most 1 + occlusion weight)
+ * lay below the second-best energy so far, so they could change neither
+ * the winner nor the margin.  They count in evals; only the samples of the
+ * views computed count in samples.  Synchronises. */
 int slf_get_work(slf_ctx *ctx, uint64_t *evals, uint64_t *samples, uint64_t *pruned);
 int slf_reset_work(slf_ctx *ctx);
 /* Waits for all work enqueued by the context. */

@@ -435,6 +435,38 @@ __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm
   return in ? fminf(ssd, T) : T;
 }
 
+// FP16 texels: each tap enters an FMA as an FP16 operand widened exactly
+// inside the instruction (v_fma_mix_f32), so the interpolation is the FP32
+// one with no separate conversions.
+template <>
+__device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, float w, float Wm1, float Hm1, int Wi,
+                                                          int Hi, __amdgpu_buffer_rsrc_t quads, uint32_t vbase,
+                                                          float r0, float g0, float b0, float T) {
+  const float rw = rcp(w);
+  const float xs = x * rw, ys = y * rw;
+  const float xc = __builtin_amdgcn_fmed3f(xs, 0.f, Wm1), yc = __builtin_amdgcn_fmed3f(ys, 0.f, Hm1);
+  const bool in = (w > 0.f) & (xc == xs) & (yc == ys);
+  const int x0 = (int)xc, y0 = (int)yc;
+  const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
+  const uint32_t off = vbase + (uint32_t)(y0 * (Wi + 1) + x0) * 8u;
+  const uint4 lo = load_u4(quads, off), hi = load_u4(quads, off + (uint32_t)(Wi + 1) * 8u);
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  const h2 rg00 = __builtin_bit_cast(h2, lo.x), b00 = __builtin_bit_cast(h2, lo.y);
+  const h2 rg10 = __builtin_bit_cast(h2, lo.z), b10 = __builtin_bit_cast(h2, lo.w);
+  const h2 rg01 = __builtin_bit_cast(h2, hi.x), b01 = __builtin_bit_cast(h2, hi.y);
+  const h2 rg11 = __builtin_bit_cast(h2, hi.z), b11 = __builtin_bit_cast(h2, hi.w);
+  const float ofx = 1.f - fx, ofy = 1.f - fy;
+  const float w00 = ofx * ofy, w10 = fx * ofy, w01 = ofx * fy, w11 = fx * fy;
+  // w00 t00 as an FMA with a +0 addend (taps and weights are >= 0, so it
+  // equals the product) keeps the first tap in the mixed-precision form too
+  const float br = fmaf(w11, (float)rg11.x, fmaf(w01, (float)rg01.x, fmaf(w10, (float)rg10.x, fmaf(w00, (float)rg00.x, 0.f))));
+  const float bg = fmaf(w11, (float)rg11.y, fmaf(w01, (float)rg01.y, fmaf(w10, (float)rg10.y, fmaf(w00, (float)rg00.y, 0.f))));
+  const float bb = fmaf(w11, (float)b11.x, fmaf(w01, (float)b01.x, fmaf(w10, (float)b10.x, fmaf(w00, (float)b00.x, 0.f))));
+  const float d0 = r0 - br, d1 = g0 - bg, d2 = b0 - bb;
+  const float ssd = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+  return in ? fminf(ssd, T) : T;
+}
+
 // Byte offset of view i's texels in the texel array (which the host keeps
 // under 4 GiB, so that one wave-uniform buffer resource covers every view).
 template <int FMT>
@@ -618,7 +650,7 @@ __device__ __forceinline__ float3 load_f3(__amdgpu_buffer_rsrc_t rs, int off) {
 struct Best {
   float E, second;
   double d, nx, ny, nz, delta;
-  int slot, evaluated, pruned;
+  int slot, evaluated, pruned, view_samples;
 };
 
 // Per-superpixel data the energy needs, uniform over the wave except the
@@ -648,15 +680,18 @@ __device__ __forceinline__ double bcast_d(double x, int l) {
 }
 
 // Energy E = E_c E_s (eqs. 3-11) of the 3D plane n . X = delta in camera r.
-// `e_floor` is the second-best energy so far: E_c <= 1 + occ (every S_i, V_i
-// and Gaussian mean is at most 1), so when E_s (1 + occ) lies below it, with
-// a margin far above FP32 rounding, the candidate can change neither the
-// winner nor the margin; then *pruned is set and the consistency loop is
-// skipped (results are unchanged).
+// `e_floor` is the second-best energy so far.  Each view's term of E_c is at
+// most 1 + occ (every S_i, V_i and Gaussian mean is at most 1), so after j of
+// the N views E_c <= (their sum + (N - j)(1 + occ)) / N.  Once E_s times that
+// bound lies below e_floor, with a margin far above FP32 rounding, the
+// candidate can change neither the winner nor the margin: *pruned is set and
+// the remaining views are skipped (results are unchanged).  *views receives
+// the number of neighbour views sampled.
 template <int FMT>
 __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, double nx, double ny, double nz,
-                        double delta, float e_floor, bool &pruned) {
+                        double delta, float e_floor, bool &pruned, int &views) {
   pruned = false;
+  views = 0;
   const int lane = threadIdx.x & (kWave - 1);
 
   if (a.energy_mode == 1) {  // data-only: -normalised TSSD of this plane
@@ -682,6 +717,7 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
                                 (float)((e.y >> 8) & 255u), (float)((e.y >> 16) & 255u), a.T255);
       }
     }
+    views = c.N;
     return -wave_sum(acc) / ((float)c.A * (float)c.N * a.T255);
   }
 
@@ -847,6 +883,12 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         const float Si = swt * c.invA;
         const float Vi = nXt > 0 ? Si * gxt * rcp((float)nXt) : 0.f;
         sum += Vi + (Y ? occ : 0.f);
+        ++views;
+        const float left = (float)(c.N - views);
+        if (Es * (sum + left * (1.f + occ)) * rcp((float)c.N) * 1.001f < e_floor) {
+          pruned = true;
+          return 0.f;
+        }
       }
     }
     Ec = sum * rcp((float)c.N);
@@ -904,8 +946,10 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
     cd.d = uni_d(cd.d);
     cd.slot = __builtin_amdgcn_readfirstlane(cd.slot);
     bool pruned;
-    const float E = energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta, b.second, pruned);
+    int views;
+    const float E = energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta, b.second, pruned, views);
     ++b.evaluated;
+    b.view_samples += views;
     if (pruned) {  // bounded below the second best: no change
       ++b.pruned;
       continue;
@@ -994,6 +1038,7 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
   b.slot = -1;
   b.evaluated = 0;
   b.pruned = 0;
+  b.view_samples = 0;
   b.d = b.nx = b.ny = b.nz = b.delta = 0.0;
 
   // Propagation (Sec. III-C, eq. 4): slot r = 0 the current plane, 1 + j ring
@@ -1108,7 +1153,7 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
       a.margin[g] = b.evaluated > 1 ? b.E - b.second : INFINITY;
     }
     atomicAdd(&a.work[0], (unsigned long long)b.evaluated);
-    atomicAdd(&a.work[1], (unsigned long long)(b.evaluated - b.pruned) * (unsigned long long)c.A * (unsigned long long)c.N);
+    atomicAdd(&a.work[1], (unsigned long long)b.view_samples * (unsigned long long)c.A);
     atomicAdd(&a.work[2], (unsigned long long)b.pruned);
   }
 }
