@@ -344,3 +344,59 @@ def test_pool_argument_errors():
     pool.detach(c)
     c.close()
     pool.close()
+
+
+def test_pool_mixed_formats_equal_solo():
+    """Rigs with different image storage share a pool: each stage runs one
+    launch per (operation, format) group, results as alone."""
+    slf = _slf()
+    _say("pool with mixed image formats")
+    ws = _rigs()
+    fmts = [slf.SLF_IMAGE_U8, slf.SLF_IMAGE_F16, slf.SLF_IMAGE_F32]
+    solo = [_solo(w, 2, image_precision=f)[0] for w, f in zip(ws, fmts)]
+    pool = slf.Pool(0)
+    ctxs = [_ctx(w, image_precision=f) for w, f in zip(ws, fmts)]
+    for j, c in enumerate(ctxs):
+        pool.attach(c)
+        pool.submit(c, slf.SLF_POOL_SOLVE, 1, 2, j)
+    pool.run()
+    for j, (w, c) in enumerate(zip(ws, ctxs)):
+        _same(_state(c, len(w.rig.views)), solo[j], "mixed formats rig %d" % j)
+        c.close()
+    pool.close()
+
+
+def test_graph_recaptured_when_the_stage_shape_changes():
+    """Solve, then propagate-only, then solve again through graph runs: each
+    shape is captured on its own and every run equals the eager result."""
+    slf = _slf()
+    _say("graph shape changes")
+    ws = _rigs()[:2]
+    eager = []
+    for w in ws:
+        c = _ctx(w)
+        c.sweep()
+        c.propagate(1, 2)
+        first = _state(c, len(w.rig.views))
+        c.propagate(3, 1)
+        second = _state(c, len(w.rig.views))
+        eager.append((first, second))
+        c.close()
+    pool = slf.Pool(0)
+    ctxs = [_ctx(w) for w in ws]
+    for c in ctxs:
+        pool.attach(c)
+    for rep in range(2):
+        for j, c in enumerate(ctxs):
+            pool.submit(c, slf.SLF_POOL_SOLVE, 1, 2, j)
+        pool.run()
+        for j, (w, c) in enumerate(zip(ws, ctxs)):
+            _same(_state(c, len(w.rig.views)), eager[j][0], "solve run %d rig %d" % (rep, j))
+        for j, c in enumerate(ctxs):
+            pool.submit(c, slf.SLF_POOL_PROPAGATE, 3, 1, 10 + j)
+        pool.run()
+        for j, (w, c) in enumerate(zip(ws, ctxs)):
+            _same(_state(c, len(w.rig.views)), eager[j][1], "propagate run %d rig %d" % (rep, j))
+    for c in ctxs:
+        c.close()
+    pool.close()
