@@ -232,6 +232,8 @@ typedef struct {
     int32_t blocks_per_cu;      /* persistent workgroups per compute unit; 0 = as many as are resident */
     int32_t use_graph;          /* 1: slf_pool_run captures its stage sequence as a HIP graph, replayed
                                    while the sequence's shape repeats (default 1) */
+    int32_t sweep_level_split;  /* sweep work items cover 1/split of a tile's levels (hypothesis chunks;
+                                   the parts are merged in level order), 1..16 (default 1) */
 } slf_pool_config;
 
 void slf_pool_default_config(slf_pool_config *cfg);
@@ -272,7 +274,7 @@ int slf_pool_run(slf_pool *pool);
 int slf_pool_poll(slf_pool *pool, uint64_t *done_tags, int max, int *n_done);
 /* Waits for all work launched by the pool. */
 int slf_pool_synchronize(slf_pool *pool);
-/* Picks sweep_level_chunk, sweep_tile and refine_tile by timing sweep and
+/* Picks sweep_level_chunk, sweep_tile, sweep_level_split and refine_tile by timing sweep and
  * refinement stages over the attached rigs (each trial capped at 2048
  * superpixels per rig), then keeps the fastest; results are cached per set of
  * (resolution, neighbours, levels, precision, views) and *from_cache (may be

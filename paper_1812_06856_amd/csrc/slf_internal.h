@@ -103,7 +103,9 @@ enum { SLF_OP_SWEEP = 0, SLF_OP_REFINE = 1 };
 struct PoolJob {
   int item_begin;  // first work item of this job within the stage
   int S;           // superpixels of the rig
-  int pad[2];
+  int split;       // sweep stages: level parts per superpixel (items = tiles x split)
+  int sp_begin;    // first superpixel of this job in the stage's superpixel order
+  int64_t part_base;  // sweep stages with split > 1: first part record of this job
   SweepArgs sweep;     // used by sweep stages
   RefineArgs refine;   // used by refinement stages
 };
@@ -114,7 +116,8 @@ constexpr int kPoolCounterStride = 16;  // ints between claim counters (one 64-b
 // [qbegin[q], qend[q]) form queue q; the waves of XCD q drain it first.
 // Read-only while the stage runs; the claim counters live elsewhere.
 struct PoolStage {
-  int njobs, tile, pad[2];
+  int njobs, tile, total_sp, pad;
+  float4 *parts;   // per (superpixel, part) {best, second, level} of split sweeps
   int qbegin[kPoolQueues], qend[kPoolQueues];
   PoolJob jobs[kPoolMaxJobs];
 };
@@ -134,8 +137,10 @@ size_t quad_bytes(int fmt);
 hipError_t launch_warm(const ViewDev *views, const int *sp_view, const int *area, const double2 *cen,
                        const float4 *colour, float4 *planes, float4 *tab, int S, double d_fb, hipStream_t st);
 // One pooled stage: a kernel that clears the stage's claim counters, then
-// the persistent kernel over `blocks` workgroups.
-hipError_t launch_pool(int op, int fmt, int kc, const PoolStage *stage, int *counters, int blocks, hipStream_t st);
+// the persistent kernel over `blocks` workgroups, then (sweeps split into
+// level parts) the kernel merging the parts.
+hipError_t launch_pool(int op, int fmt, int kc, bool merge, const PoolStage *stage, int *counters, int blocks,
+                       hipStream_t st);
 // Workgroups of the pooled kernel resident per compute unit.
 int pool_occupancy(int op, int fmt, int kc);
 

@@ -507,30 +507,17 @@ __host__ __device__ inline int launch_blocks(int nblocks) {
 // depth q_k has inverse-depth row (0, 0, q_k)).  Per-level lane partials are
 // summed by a butterfly and the running argmin keeps the smallest level on
 // ties.
+// Costs of levels [k_begin, k_end) of superpixel g: the smallest (ties: the
+// lowest level) and the second smallest, uniform over the wave.
 template <int FMT, int KC>
-__device__ __forceinline__ void sweep_sp(const SweepArgs &a, const int g) {
+__device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, const int v, const int s,
+                                             const ViewDev &vw, const int A, const int k_begin, const int k_end,
+                                             float &best, float &second, int &kbest) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int v = a.sp_view[g];
-  const ViewDev &vw = a.views[v];
-  const int s = g - vw.sp_off;
-  const int A = a.area[g];
-  if (A == 0) {
-    if (lane == 0) {
-      a.planes[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-      a.tab[2 * g] = make_float4(0.f, 0.f, 0.f, 0.f);
-      a.tab[2 * g + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-      a.cost[g] = 0.f;
-      a.choice[g] = -1;
-      a.margin[g] = 0.f;
-    }
-    return;
-  }
   const int N = vw.n_pairs;
   const int P = A * N;
   const int poff = a.px_off[g];
-  float best = INFINITY, second = INFINITY;
-  int kbest = 0;
-  for (int k0 = 0; k0 < a.levels; k0 += KC) {
+  for (int k0 = k_begin; k0 < k_end; k0 += KC) {
     float q[KC];
 #pragma unroll
     for (int j = 0; j < KC; ++j) q[j] = (float)level_q(a.seed, a.jitter, a.qmin, a.dq, v, s, k0 + j);
@@ -583,7 +570,7 @@ __device__ __forceinline__ void sweep_sp(const SweepArgs &a, const int g) {
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       const float C = wave_sum(acc[kk]);
-      if (k0 + kk < a.levels) {
+      if (k0 + kk < k_end) {
         if (C < best) {
           second = best;
           best = C;
@@ -594,16 +581,95 @@ __device__ __forceinline__ void sweep_sp(const SweepArgs &a, const int g) {
       }
     }
   }
-  if (lane == 0) {
-    const double qb = level_q(a.seed, a.jitter, a.qmin, a.dq, v, s, kbest);
-    a.planes[g] = make_float4((float)(1.0 / qb), 0.f, 0.f, 1.f);
-    a.tab[2 * g] = a.colour[g];
-    a.tab[2 * g + 1] = make_float4(0.f, 0.f, (float)qb, 0.f);
-    const float norm = 1.f / ((float)A * (float)N * a.T255);
-    a.cost[g] = best * norm;
-    a.choice[g] = kbest;
-    a.margin[g] = a.levels > 1 ? (second - best) * norm : INFINITY;
+}
+
+// Sweep outputs of superpixel g (one lane): the fronto-parallel plane of
+// the best level, its {colour, inverse-depth row} record, normalised cost,
+// level and margin.
+__device__ __forceinline__ void sweep_finish(const SweepArgs &a, const int g, const int v, const int s, const int A,
+                                             const int N, const float best, const float second, const int kbest) {
+  const double qb = level_q(a.seed, a.jitter, a.qmin, a.dq, v, s, kbest);
+  a.planes[g] = make_float4((float)(1.0 / qb), 0.f, 0.f, 1.f);
+  a.tab[2 * g] = a.colour[g];
+  a.tab[2 * g + 1] = make_float4(0.f, 0.f, (float)qb, 0.f);
+  const float norm = 1.f / ((float)A * (float)N * a.T255);
+  a.cost[g] = best * norm;
+  a.choice[g] = kbest;
+  a.margin[g] = a.levels > 1 ? (second - best) * norm : INFINITY;
+}
+
+__device__ __forceinline__ void sweep_empty(const SweepArgs &a, const int g) {
+  a.planes[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+  a.tab[2 * g] = make_float4(0.f, 0.f, 0.f, 0.f);
+  a.tab[2 * g + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+  a.cost[g] = 0.f;
+  a.choice[g] = -1;
+  a.margin[g] = 0.f;
+}
+
+template <int FMT, int KC>
+__device__ __forceinline__ void sweep_sp(const SweepArgs &a, const int g) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int v = a.sp_view[g];
+  const ViewDev &vw = a.views[v];
+  const int s = g - vw.sp_off;
+  const int A = a.area[g];
+  if (A == 0) {
+    if (lane == 0) sweep_empty(a, g);
+    return;
   }
+  float best = INFINITY, second = INFINITY;
+  int kbest = 0;
+  sweep_levels<FMT, KC>(a, g, v, s, vw, A, 0, a.levels, best, second, kbest);
+  if (lane == 0) sweep_finish(a, g, v, s, A, vw.n_pairs, best, second, kbest);
+}
+
+// Levels of part `part` of `split` (contiguous, whole level chunks) of
+// superpixel g; writes {best, second, level} to parts[part].  Empty
+// superpixels are written by the finalize step.
+__device__ __forceinline__ int part_levels(int levels, int split, int kc) {
+  return ((levels + split - 1) / split + kc - 1) / kc * kc;
+}
+template <int FMT, int KC>
+__device__ __forceinline__ void sweep_part(const SweepArgs &a, const int g, const int part, const int split,
+                                           float4 *parts) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int v = a.sp_view[g];
+  const ViewDev &vw = a.views[v];
+  const int s = g - vw.sp_off;
+  const int A = a.area[g];
+  if (A == 0) return;
+  const int per = part_levels(a.levels, split, KC);
+  const int kb = part * per, ke = min(a.levels, kb + per);
+  float best = INFINITY, second = INFINITY;
+  int kbest = 0;
+  if (kb < ke) sweep_levels<FMT, KC>(a, g, v, s, vw, A, kb, ke, best, second, kbest);
+  if (lane == 0) parts[part] = make_float4(best, second, __int_as_float(kbest), 0.f);
+}
+
+// Merges the parts of superpixel g in level order: the two smallest costs
+// and the level of the first smallest, as one pass over all levels gives.
+__device__ __forceinline__ void sweep_merge(const SweepArgs &a, const int g, const int split, const float4 *parts) {
+  const int v = a.sp_view[g];
+  const ViewDev &vw = a.views[v];
+  const int A = a.area[g];
+  if (A == 0) {
+    sweep_empty(a, g);
+    return;
+  }
+  float best = INFINITY, second = INFINITY;
+  int kbest = 0;
+  for (int p = 0; p < split; ++p) {
+    const float4 r = parts[p];
+    if (r.x < best) {
+      second = fminf(best, r.y);
+      best = r.x;
+      kbest = __float_as_int(r.z);
+    } else {
+      second = fminf(second, r.x);
+    }
+  }
+  sweep_finish(a, g, v, g - vw.sp_off, A, vw.n_pairs, best, second, kbest);
 }
 
 #ifndef SLF_LEVEL_CHUNK
@@ -1221,13 +1287,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SL
       }
       lo = __builtin_amdgcn_readfirstlane(lo);
       const PoolJob &J = *(const PoolJob *)&st.jobs[lo];
-      const int g0 = (item - J.item_begin) * tile;
-      const int g1 = min(g0 + tile, J.S);
-      for (int g = g0; g < g1; ++g) {
-        if constexpr (OP == SLF_OP_SWEEP)
-          sweep_sp<FMT, KC>(J.sweep, g);
-        else
-          refine_sp<FMT>(J.refine, g, s_list[wid], s_pix[wid]);
+      if constexpr (OP == SLF_OP_SWEEP) {
+        const int split = J.split;
+        const int t = item - J.item_begin;
+        const int part = t % split;
+        const int g0 = (t / split) * tile;
+        const int g1 = min(g0 + tile, J.S);
+        for (int g = g0; g < g1; ++g) {
+          if (split == 1)
+            sweep_sp<FMT, KC>(J.sweep, g);
+          else
+            sweep_part<FMT, KC>(J.sweep, g, part, split, st.parts + J.part_base + (int64_t)g * split);
+        }
+      } else {
+        const int g0 = (item - J.item_begin) * tile;
+        const int g1 = min(g0 + tile, J.S);
+        for (int g = g0; g < g1; ++g) refine_sp<FMT>(J.refine, g, s_list[wid], s_pix[wid]);
       }
     }
   }
@@ -1267,11 +1342,33 @@ int pool_occupancy(int op, int fmt, int kc) {
   return n;
 }
 
-hipError_t launch_pool(int op, int fmt, int kc, const PoolStage *stage, int *counters, int blocks, hipStream_t st) {
+// Merges the level parts of every superpixel of a split sweep stage (one
+// thread per superpixel, grid-stride, so the launch shape does not depend on
+// the batch).
+__global__ __launch_bounds__(256) void k_sweep_merge(const PoolStage *__restrict__ stage_ptr) {
+  ConstStage &st = *(ConstStage *)stage_ptr;
+  const int njobs = st.njobs, total = st.total_sp;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (st.jobs[mid].sp_begin <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    const PoolJob &J = *(const PoolJob *)&st.jobs[lo];
+    if (J.split <= 1) continue;
+    const int g = i - J.sp_begin;
+    sweep_merge(J.sweep, g, J.split, st.parts + J.part_base + (int64_t)g * J.split);
+  }
+}
+
+hipError_t launch_pool(int op, int fmt, int kc, bool merge, const PoolStage *stage, int *counters, int blocks,
+                       hipStream_t st) {
   hipLaunchKernelGGL(k_pool_reset, dim3(1), dim3(64), 0, st, counters);
   void *args[] = {(void *)&stage, (void *)&counters};
   const hipError_t e = hipLaunchKernel(pool_kernel(op, fmt, kc), dim3(blocks), dim3(kBlock), args, 0, st);
   if (e != hipSuccess) return e;
+  if (merge) hipLaunchKernelGGL(k_sweep_merge, dim3(1024), dim3(256), 0, st, stage);
   return hipGetLastError();
 }
 

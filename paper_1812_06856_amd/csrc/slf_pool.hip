@@ -65,6 +65,8 @@ struct slf_pool {
   slf_pool_config cfg;
   PoolStage *d_stages = nullptr, *h_stages = nullptr;
   int *d_counters = nullptr;
+  float4 *d_parts = nullptr;  // level-part records of split sweeps
+  int64_t parts_cap = 0, parts_fill = 0;
   hipEvent_t uploaded[kRegions] = {};
   int half = 0;
   hipGraphExec_t gexec = nullptr;
@@ -95,6 +97,7 @@ void default_config(slf_pool_config *c) {
   c->refine_tile = 1;
   c->blocks_per_cu = 0;
   c->use_graph = 1;
+  c->sweep_level_split = 1;
 }
 
 int config_check(slf_pool *P, const slf_pool_config *c) {
@@ -106,6 +109,8 @@ int config_check(slf_pool *P, const slf_pool_config *c) {
   if (c->sweep_tile < 1 || c->sweep_tile > 64 || c->refine_tile < 1 || c->refine_tile > 64)
     return P->fail(SLF_EINVAL, "tiles must be in [1, 64]");
   if (c->blocks_per_cu < 0 || c->blocks_per_cu > 64) return P->fail(SLF_EINVAL, "blocks_per_cu must be in [0, 64]");
+  if (c->sweep_level_split < 1 || c->sweep_level_split > 16)
+    return P->fail(SLF_EINVAL, "sweep_level_split must be in [1, 16]");
   return SLF_OK;
 }
 
@@ -137,19 +142,28 @@ std::vector<Group> plan_stage(std::vector<Req *> &reqs) {
 // Writes the stage table of one group (at most kPoolMaxJobs requests) and
 // advances its requests.  s_cap limits the superpixels of every job (the
 // autotuner's trials); 0 = all.
-void fill_stage(const slf_pool *P, PoolStage &st, const Group &g, int s_cap, bool advance) {
+void fill_stage(slf_pool *P, PoolStage &st, const Group &g, int s_cap, bool advance) {
   const int tile = g.op == SLF_OP_SWEEP ? P->cfg.sweep_tile : P->cfg.refine_tile;
+  const int split = g.op == SLF_OP_SWEEP ? P->cfg.sweep_level_split : 1;
   st.njobs = (int)g.reqs.size();
   st.tile = tile;
-  st.pad[0] = st.pad[1] = 0;
-  int items = 0;
+  st.pad = 0;
+  st.parts = P->d_parts;
+  int items = 0, sp = 0;
   for (int j = 0; j < st.njobs; ++j) {
     Req *r = g.reqs[j];
     PoolJob &J = st.jobs[j];
     std::memset(&J, 0, sizeof J);
     J.item_begin = items;
     J.S = s_cap > 0 ? std::min(r->rig->S, s_cap) : r->rig->S;
-    items += (J.S + tile - 1) / tile;
+    J.split = split;
+    J.sp_begin = sp;
+    if (split > 1) {
+      J.part_base = P->parts_fill;
+      P->parts_fill += (int64_t)J.S * split;
+    }
+    sp += J.S;
+    items += (J.S + tile - 1) / tile * split;
     if (g.op == SLF_OP_SWEEP) {
       sweep_args(r->rig, J.sweep);
       if (advance) {
@@ -164,6 +178,7 @@ void fill_stage(const slf_pool *P, PoolStage &st, const Group &g, int s_cap, boo
       }
     }
   }
+  st.total_sp = sp;
   for (int q = 0; q < kPoolQueues; ++q) {
     st.qbegin[q] = (int)((int64_t)items * q / kPoolQueues);
     st.qend[q] = (int)((int64_t)items * (q + 1) / kPoolQueues);
@@ -186,8 +201,31 @@ int upload(slf_pool *P, int r, int n) {
   return SLF_OK;
 }
 
+// Part records the sweep groups of `groups` need (split sweeps), grown
+// before any stage table points at the buffer; in-flight work that may use
+// the old buffer is waited for first.
+int reserve_parts(slf_pool *P, const std::vector<Group> &groups, int s_cap) {
+  P->parts_fill = 0;
+  if (P->cfg.sweep_level_split <= 1) return SLF_OK;
+  int64_t need = 0;
+  for (const Group &g : groups)
+    if (g.op == SLF_OP_SWEEP)
+      for (const Req *r : g.reqs) need += (int64_t)(s_cap > 0 ? std::min(r->rig->S, s_cap) : r->rig->S);
+  need *= P->cfg.sweep_level_split;
+  if (need <= P->parts_cap) return SLF_OK;
+  if (hipStreamSynchronize(P->stream) != hipSuccess) return P->fail(SLF_EDEVICE, "hipStreamSynchronize failed");
+  if (P->d_parts) (void)hipFree(P->d_parts);
+  P->d_parts = nullptr;
+  P->parts_cap = 0;
+  if (hipMalloc((void **)&P->d_parts, sizeof(float4) * need) != hipSuccess)
+    return P->fail(SLF_ENOMEM, "pool part records: %lld bytes", (long long)(sizeof(float4) * need));
+  P->parts_cap = need;
+  return SLF_OK;
+}
+
 int launch_group(slf_pool *P, const Group &g, int slot) {
-  const hipError_t e = launch_pool(g.op, g.fmt, P->cfg.sweep_level_chunk, P->d_stages + slot,
+  const bool merge = g.op == SLF_OP_SWEEP && P->cfg.sweep_level_split > 1;
+  const hipError_t e = launch_pool(g.op, g.fmt, P->cfg.sweep_level_chunk, merge, P->d_stages + slot,
                                    P->d_counters + slot * kPoolQueues * kPoolCounterStride,
                                    blocks_for(P, g.op, g.fmt), P->stream);
   if (e != hipSuccess) return P->fail(SLF_EDEVICE, "pooled launch: %s", hipGetErrorString(e));
@@ -222,6 +260,7 @@ int one_step(slf_pool *P) {
   const int r = P->half;
   int rc;
   if ((rc = wait_region(P, r))) return rc;
+  if ((rc = reserve_parts(P, groups, 0))) return rc;
   const int base = region_base(r);
   for (size_t i = 0; i < groups.size(); ++i) fill_stage(P, P->h_stages[base + i], groups[i], 0, true);
   if ((rc = upload(P, r, (int)groups.size()))) return rc;
@@ -264,8 +303,10 @@ int run_graph(slf_pool *P) {
   for (size_t i = 0; i < reqs.size(); ++i) *reqs[i] = saved[i];  // rewind the shadow run
   sig.push_back(P->cfg.sweep_level_chunk);
   sig.push_back(P->cfg.blocks_per_cu);
+  sig.push_back(P->cfg.sweep_level_split);
   int rc;
   if ((rc = wait_region(P, 2))) return rc;
+  if ((rc = reserve_parts(P, all, 0))) return rc;
   const int base = region_base(2);
   for (size_t i = 0; i < all.size(); ++i) fill_stage(P, P->h_stages[base + i], all[i], 0, true);
   if ((rc = upload(P, 2, (int)all.size()))) return rc;
@@ -331,6 +372,7 @@ int time_stage(slf_pool *P, int op, int s_cap, int reps, float *ms) {
   for (int rep = 0; rep < reps; ++rep) {
     const int r = P->half;
     if ((rc = wait_region(P, r))) return rc;
+    if ((rc = reserve_parts(P, groups, s_cap))) return rc;
     const int base = region_base(r);
     for (size_t i = 0; i < groups.size(); ++i) fill_stage(P, P->h_stages[base + i], groups[i], s_cap, false);
     if ((rc = upload(P, r, (int)groups.size()))) return rc;
@@ -415,6 +457,7 @@ int slf_pool_destroy(slf_pool *P) {
     if (e) (void)hipEventDestroy(e);
   if (P->d_stages) (void)hipFree(P->d_stages);
   if (P->d_counters) (void)hipFree(P->d_counters);
+  if (P->d_parts) (void)hipFree(P->d_parts);
   if (P->h_stages) (void)hipHostFree(P->h_stages);
   if (P->own) (void)hipStreamDestroy(P->own);
   delete P;
@@ -599,17 +642,20 @@ int slf_pool_autotune(slf_pool *P, int *from_cache) {
   float best_ms = 1e30f;
   int rc;
   for (int kc : {4, 8, 16})
-    for (int tile : {1, 2, 4}) {
-      P->cfg.sweep_level_chunk = kc;
-      P->cfg.sweep_tile = tile;
-      float ms = 0.f;
-      if ((rc = time_stage(P, SLF_OP_SWEEP, s_cap, 2, &ms))) return rc;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best.sweep_level_chunk = kc;
-        best.sweep_tile = tile;
+    for (int tile : {1, 2})
+      for (int split : {1, 2, 4}) {
+        P->cfg.sweep_level_chunk = kc;
+        P->cfg.sweep_tile = tile;
+        P->cfg.sweep_level_split = split;
+        float ms = 0.f;
+        if ((rc = time_stage(P, SLF_OP_SWEEP, s_cap, 2, &ms))) return rc;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best.sweep_level_chunk = kc;
+          best.sweep_tile = tile;
+          best.sweep_level_split = split;
+        }
       }
-    }
   P->cfg = best;
   // the refinement trials read a swept state
   {

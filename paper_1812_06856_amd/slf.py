@@ -45,7 +45,8 @@ class slf_params(ctypes.Structure):
 class slf_pool_config(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("sweep_level_chunk", ctypes.c_int32),
                 ("sweep_tile", ctypes.c_int32), ("refine_tile", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("sweep_level_split", ctypes.c_int32)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}

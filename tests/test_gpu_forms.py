@@ -400,3 +400,25 @@ def test_graph_recaptured_when_the_stage_shape_changes():
     for c in ctxs:
         c.close()
     pool.close()
+
+
+@pytest.mark.parametrize("split,kc", [(2, 8), (3, 4), (4, 8)])
+def test_pool_level_split_equals_solo(split, kc):
+    """Sweep work items of 1/split of the levels (hypothesis chunks) merged in
+    level order give the single-pass result bit for bit, including parts left
+    empty when the levels do not divide evenly."""
+    slf = _slf()
+    _say("pool level split %d, chunk %d" % (split, kc))
+    ws = _rigs()
+    solo = [_solo(w, 1)[0] for w in ws]
+    pool = slf.Pool(0)
+    pool.set_config(slf.default_pool_config(sweep_level_split=split, sweep_level_chunk=kc, sweep_tile=2))
+    ctxs = [_ctx(w) for w in ws]
+    for j, c in enumerate(ctxs):
+        pool.attach(c)
+        pool.submit(c, slf.SLF_POOL_SOLVE, 1, 1, j)
+    pool.run()
+    for j, (w, c) in enumerate(zip(ws, ctxs)):
+        _same(_state(c, len(w.rig.views)), solo[j], "split %d rig %d" % (split, j))
+        c.close()
+    pool.close()
