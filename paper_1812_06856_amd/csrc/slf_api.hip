@@ -114,6 +114,7 @@ void free_all(slf_ctx *c) {
   free_sp(c);
   dfree(c->d_rgb);
   dfree(c->d_labels);
+  dfree(c->d_lab16);
   if (c->d_quads) (void)hipFree(c->d_quads);
   c->d_quads = nullptr;
   c->quads_bytes = 0;
@@ -282,7 +283,10 @@ int slf::ensure_setup(slf_ctx *c) {
     bool all_planes = true;
     for (const auto &v : c->vh) all_planes = all_planes && v.has_planes;
     c->warm_ok = kept && same_cells && all_planes;
-    HIP_OR_FAIL(c, launch_sp_build(c->d_views, c->views_h.data(), c->V, c->d_labels, c->d_rgb, c->S, c->d_count,
+    c->lab16_ok = true;
+    for (const auto &v : c->vh) c->lab16_ok = c->lab16_ok && (int64_t)v.gw * v.gh <= 65536;
+    HIP_OR_FAIL(c, launch_sp_build(c->d_views, c->views_h.data(), c->V, c->d_labels,
+                                   c->lab16_ok ? c->d_lab16 : nullptr, c->d_rgb, c->S, c->d_count,
                                    c->d_bbox, c->d_px_off, c->d_scan, c->d_px, c->d_area, c->d_centroid,
                                    c->d_centroid_d, c->d_colour, c->d_sp_view, c->d_err, c->stream));
     int herr = 0;
@@ -319,7 +323,7 @@ int slf::footprint(const slf_ctx *c, uint64_t *bytes) {
     pairs += v.nbrs.size();
   }
   uint64_t b = 0;
-  b += px * 3 + px * sizeof(int);                                 // images, labels
+  b += px * (3 + sizeof(int) + sizeof(uint16_t));                 // images, labels (32 and 16 bits)
   b += texels * quad_bytes(c->p.image_precision);                 // bilinear texels
   b += sizeof(ViewDev) * c->V + sizeof(PairDev) * pairs + 64;     // geometry, flags, counters
   b += S * (4 * sizeof(int) + sizeof(int4) + sizeof(float2) + sizeof(double2) + sizeof(float4));
@@ -383,6 +387,7 @@ void slf::refine_args(const slf_ctx *c, int iter, RefineArgs &a) {
   a.centroid_d = c->d_centroid_d;
   a.colour = c->d_colour;
   a.labels = c->d_labels;
+  a.lab16 = c->lab16_ok ? c->d_lab16 : nullptr;
   a.quads = c->d_quads;
   a.quad_bytes = (uint32_t)c->quads_bytes;
   a.energy = c->d_energy;
@@ -551,6 +556,7 @@ int slf_set_cameras(slf_ctx *c, int n_views, const int32_t *wh, const double *K,
   free_sp(c);
   dfree(c->d_rgb);
   dfree(c->d_labels);
+  dfree(c->d_lab16);
   if (c->d_quads) (void)hipFree(c->d_quads);
   c->d_quads = nullptr;
   c->quads_bytes = 0;
@@ -560,6 +566,7 @@ int slf_set_cameras(slf_ctx *c, int n_views, const int32_t *wh, const double *K,
   int rc;
   if ((rc = ensure_alloc(c, (size_t)total * 3, (void **)&c->d_rgb))) return rc;
   if ((rc = ensure_alloc(c, (size_t)total * sizeof(int), (void **)&c->d_labels))) return rc;
+  if ((rc = ensure_alloc(c, (size_t)total * sizeof(uint16_t), (void **)&c->d_lab16))) return rc;
   c->geom_dirty = true;
   c->sp_dirty = true;
   c->quads_dirty = true;

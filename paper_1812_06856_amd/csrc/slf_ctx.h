@@ -42,6 +42,8 @@ struct slf_ctx {
   // per-pixel device buffers
   uint8_t *d_rgb = nullptr;
   int *d_labels = nullptr;
+  uint16_t *d_lab16 = nullptr;  // the labels as 16 bits, for the refinement's gathers
+  bool lab16_ok = false;        // every view has at most 65536 grid cells
   void *d_quads = nullptr;
   size_t quads_bytes = 0;
   int quads_fmt = -1;

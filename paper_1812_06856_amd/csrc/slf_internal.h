@@ -78,6 +78,7 @@ struct RefineArgs {
   const double2 *centroid_d;  // centroids in FP64
   const float4 *colour;   // mean colour in [0,1]
   const int *labels;      // all views
+  const uint16_t *lab16;  // the same labels as 16 bits, or null when a view has more than 65536 cells
   const void *quads;      // images (data-only energy mode)
   uint32_t quad_bytes;    // bytes of texels over all views (< 4 GiB)
   const float4 *planesA;  // state read
@@ -125,7 +126,7 @@ struct PoolStage {
 // Host-side launchers (slf_kernels.hip).
 hipError_t launch_quads(int fmt, const uint8_t *rgb, int64_t rgb_stride, int W, int H, void *quads,
                         int64_t quad_off, hipStream_t st);
-hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V, const int *labels,
+hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V, const int *labels, uint16_t *lab16,
                            const uint8_t *rgb, int S, int *count, int4 *bbox, int *px_off, int *scan_tmp,
                            PixEntry *px, int *area, float2 *centroid, double2 *centroid_d, float4 *colour,
                            int *sp_view, int *err, hipStream_t st);

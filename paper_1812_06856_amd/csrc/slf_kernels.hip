@@ -8,6 +8,8 @@
 #include <limits.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "slf_internal.h"
 
 namespace slf {
@@ -232,8 +234,9 @@ __global__ __launch_bounds__(256) void k_sp_reset(const ViewDev *views, int V, i
 }
 
 // Each horizontal run of equal labels is counted once, by its first pixel.
-__global__ __launch_bounds__(256) void k_sp_count(const int *labels, int W, int H, int K, int sp_off, int *count,
-                                                  int4 *bbox, int *err) {
+// With lab16 non-null (K <= 65536) every pixel also stores its label as 16 bits.
+__global__ __launch_bounds__(256) void k_sp_count(const int *labels, uint16_t *lab16, int W, int H, int K, int sp_off,
+                                                  int *count, int4 *bbox, int *err) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)W * H) return;
   const int x = (int)(idx % W), y = (int)(idx / W);
@@ -242,6 +245,7 @@ __global__ __launch_bounds__(256) void k_sp_count(const int *labels, int W, int 
     atomicOr(err, 1);
     return;
   }
+  if (lab16) lab16[idx] = (uint16_t)l;
   if (x > 0 && labels[idx - 1] == l) return;
   int len = 1;
   while (x + len < W && labels[idx + len] == l) ++len;
@@ -378,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_sp_fill(const ViewDev *views, const 
   }
 }
 
-hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V, const int *labels,
+hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V, const int *labels, uint16_t *lab16,
                            const uint8_t *rgb, int S, int *count, int4 *bbox, int *px_off, int *scan_tmp,
                            PixEntry *px, int *area, float2 *centroid, double2 *centroid_d, float4 *colour,
                            int *sp_view, int *err, hipStream_t st) {
@@ -387,8 +391,8 @@ hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V
   for (int v = 0; v < V; ++v) {
     const ViewDev &vw = views_h[v];
     const int64_t n = (int64_t)vw.W * vw.H;
-    hipLaunchKernelGGL(k_sp_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, labels + vw.pix_off, vw.W,
-                       vw.H, vw.gw * vw.gh, vw.sp_off, count, bbox, err);
+    hipLaunchKernelGGL(k_sp_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, labels + vw.pix_off,
+                       lab16 ? lab16 + vw.pix_off : nullptr, vw.W, vw.H, vw.gw * vw.gh, vw.sp_off, count, bbox, err);
   }
   const int per = kScanThreads * kScanItems;
   const int nb = (S + per - 1) / per;
@@ -868,7 +872,11 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         const ViewDev &vi = a.views[a.pairs[vw.pair_off + base + jv].i];
         const float Wm1 = (float)(vi.W - 1), Hm1 = (float)(vi.H - 1);
         const uint32_t Wv = (uint32_t)vi.W;
-        const __amdgpu_buffer_rsrc_t lab_rs = buffer_rsrc(a.labels + vi.pix_off, 4u * (uint32_t)vi.W * (uint32_t)vi.H);
+        // 16-bit labels when every view has at most 65536 cells: half the
+        // bytes of the label windows the gathers touch.
+        const uint32_t npx = (uint32_t)vi.W * (uint32_t)vi.H;
+        const __amdgpu_buffer_rsrc_t lab_rs =
+            a.lab16 ? buffer_rsrc(a.lab16 + vi.pix_off, 2u * npx) : buffer_rsrc(a.labels + vi.pix_off, 4u * npx);
         const __amdgpu_buffer_rsrc_t tab_rs = buffer_rsrc(a.tabA + 2 * vi.sp_off, 32u * (uint32_t)(vi.gw * vi.gh));
         float sw = 0.f, gx = 0.f;
         int nX = 0;
@@ -897,8 +905,11 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           q.pix = (uint32_t)(int)vc * Wv + (uint32_t)(int)uc;
           return q;
         };
-        auto label = [&](const Proj &q) {
-          return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(lab_rs, (int)(4u * q.pix), 0, 0);
+        auto label = [&](const Proj &q, auto narrow) -> uint32_t {
+          if constexpr (decltype(narrow)::value)
+            return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(lab_rs, (int)(2u * q.pix), 0, 0);
+          else
+            return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(lab_rs, (int)(4u * q.pix), 0, 0);
         };
         auto accumulate = [&](const Proj &q, const float3 Cl, const float3 gt) {
           const float dr = c.Cs.x - Cl.x, dg = c.Cs.y - Cl.y, db = c.Cs.z - Cl.z;
@@ -915,33 +926,39 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           gx += (q.seen & vis & front) ? gk : 0.f;
           anyY |= q.seen & !vis;
         };
-        auto one = [&](uint32_t uv) {
+        auto one = [&](uint32_t uv, auto narrow) {
           const Proj q = project(uv);
-          const uint32_t l = label(q);
+          const uint32_t l = label(q, narrow);
           accumulate(q, load_f3(tab_rs, (int)(32u * l)), load_f3(tab_rs, (int)(32u * l + 16u)));
         };
         // kChains pixels per lane per pass keep that many gather chains in
         // flight; each lane still accumulates its pixels in order.
-        const int n_lds = min(c.A, kLdsPix);
-        int p = lane;
-        for (; p + (kChains - 1) * kWave < n_lds; p += kChains * kWave) {
-          Proj q[kChains];
-          uint32_t l[kChains];
-          float3 C[kChains], G[kChains];
+        auto samples = [&](auto narrow) {
+          const int n_lds = min(c.A, kLdsPix);
+          int p = lane;
+          for (; p + (kChains - 1) * kWave < n_lds; p += kChains * kWave) {
+            Proj q[kChains];
+            uint32_t l[kChains];
+            float3 C[kChains], G[kChains];
 #pragma unroll
-          for (int k = 0; k < kChains; ++k) q[k] = project(c.pix_lds[p + k * kWave]);
+            for (int k = 0; k < kChains; ++k) q[k] = project(c.pix_lds[p + k * kWave]);
 #pragma unroll
-          for (int k = 0; k < kChains; ++k) l[k] = label(q[k]);
+            for (int k = 0; k < kChains; ++k) l[k] = label(q[k], narrow);
 #pragma unroll
-          for (int k = 0; k < kChains; ++k) {
-            C[k] = load_f3(tab_rs, (int)(32u * l[k]));
-            G[k] = load_f3(tab_rs, (int)(32u * l[k] + 16u));
+            for (int k = 0; k < kChains; ++k) {
+              C[k] = load_f3(tab_rs, (int)(32u * l[k]));
+              G[k] = load_f3(tab_rs, (int)(32u * l[k] + 16u));
+            }
+#pragma unroll
+            for (int k = 0; k < kChains; ++k) accumulate(q[k], C[k], G[k]);
           }
-#pragma unroll
-          for (int k = 0; k < kChains; ++k) accumulate(q[k], C[k], G[k]);
-        }
-        for (; p < n_lds; p += kWave) one(c.pix_lds[p]);
-        for (p = kLdsPix + lane; p < c.A; p += kWave) one(a.px[c.poff + p].x);
+          for (; p < n_lds; p += kWave) one(c.pix_lds[p], narrow);
+          for (p = kLdsPix + lane; p < c.A; p += kWave) one(a.px[c.poff + p].x, narrow);
+        };
+        if (a.lab16)
+          samples(std::true_type{});
+        else
+          samples(std::false_type{});
         const float swt = wave_sum(sw);
         const float gxt = wave_sum(gx);
         const int nXt = wave_sum_i(nX);
