@@ -709,7 +709,23 @@ constexpr int kLdsPix = 1024;  // pixels of a superpixel staged in LDS (the rest
 #endif
 constexpr int kChains = SLF_REFINE_CHAINS;  // independent gather chains per lane in the energy loop
 
+// An entry of a table that no kernel writes while it reads it (geometry,
+// superpixel statistics, the state being read), accessed through the
+// constant address space: at a wave-uniform index the compiler then always
+// emits a scalar load, whatever it can prove about the stores around it.
+template <class T>
+__device__ __forceinline__ const T &ro_at(const T *p, int64_t i) {
+  typedef const __attribute__((address_space(4))) T CT;
+  return *(const T *)&((CT *)p)[i];
+}
+
 typedef __attribute__((address_space(3))) uint32_t LdsU32;
+
+// Makes earlier LDS writes of any lane of this wave visible to its later reads.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 __device__ __forceinline__ float3 load_f3(__amdgpu_buffer_rsrc_t rs, int off) {
   typedef float f3v __attribute__((ext_vector_type(3)));
@@ -717,30 +733,105 @@ __device__ __forceinline__ float3 load_f3(__amdgpu_buffer_rsrc_t rs, int off) {
   return make_float3(v.x, v.y, v.z);
 }
 
+// The best plane so far (in the wave's LDS) and its depth at the centroid.
+struct BestPlane {
+  double nx, ny, nz, delta, d;
+};
+typedef __attribute__((address_space(3))) BestPlane LdsBest;
+
+// Energies, slot and counters of the running winner (uniform, in scalar registers).
 struct Best {
   float E, second;
-  double d, nx, ny, nz, delta;
   int slot, evaluated, pruned, view_samples;
 };
 
-// Per-superpixel data the energy needs, uniform over the wave except the
-// ring fields, which lane j < 8 holds for ring neighbour j.  Geometry that
-// defines candidate planes (rays through centroids, normals) is FP64.
+// Ring neighbour j of the superpixel (eq. 5), held in LDS.
+struct RingEntry {
+  double rx, ry, rz;  // K_r^-1 (c_j, 1)
+  double d;           // centroid depth in state A
+  float w;            // omega(C_s, C_j) scaled by 1 / max_j omega (same ratio in eq. 5)
+  int cell;           // -1 if outside the grid or empty
+};
+// Per-(candidate, neighbour view) projection constants, composed in FP64 and
+// stored in FP32 (see energy()).
+struct ViewConst {
+  float ax, axu, axv, ay, ayu, ayv, aw, awu, awv;
+  int X0, Y0, pad;
+};
+constexpr int kViewsPerPass = 16;  // neighbour views whose constants are composed at once
+typedef __attribute__((address_space(3))) RingEntry LdsRing;
+typedef __attribute__((address_space(3))) ViewConst LdsViewConst;
+
+// Field-wise copies between registers and LDS.
+__device__ __forceinline__ RingEntry lds_get(const LdsRing *p) {
+  RingEntry r;
+  r.rx = p->rx;
+  r.ry = p->ry;
+  r.rz = p->rz;
+  r.d = p->d;
+  r.w = p->w;
+  r.cell = p->cell;
+  return r;
+}
+__device__ __forceinline__ void lds_put(LdsRing *p, const RingEntry &r) {
+  p->rx = r.rx;
+  p->ry = r.ry;
+  p->rz = r.rz;
+  p->d = r.d;
+  p->w = r.w;
+  p->cell = r.cell;
+}
+__device__ __forceinline__ ViewConst lds_get(const LdsViewConst *p) {
+  ViewConst q;
+  q.ax = p->ax;
+  q.axu = p->axu;
+  q.axv = p->axv;
+  q.ay = p->ay;
+  q.ayu = p->ayu;
+  q.ayv = p->ayv;
+  q.aw = p->aw;
+  q.awu = p->awu;
+  q.awv = p->awv;
+  q.X0 = p->X0;
+  q.Y0 = p->Y0;
+  q.pad = 0;
+  return q;
+}
+__device__ __forceinline__ void lds_put(LdsViewConst *p, const ViewConst &q) {
+  p->ax = q.ax;
+  p->axu = q.axu;
+  p->axv = q.axv;
+  p->ay = q.ay;
+  p->ayu = q.ayu;
+  p->ayv = q.ayv;
+  p->aw = q.aw;
+  p->awu = q.awu;
+  p->awv = q.awv;
+  p->X0 = q.X0;
+  p->Y0 = q.Y0;
+}
+
+// Per-superpixel data the energy needs, uniform over the wave.  Geometry
+// that defines candidate planes (rays through centroids, normals) is FP64.
+// Per-lane tables live in the wave's LDS space, so that they hold no
+// registers while the samples run.
 struct SpCtx {
   int g, v, s, A, N, poff;
   int ub, vb;                // centroid rounded to the nearest pixel
   float invA;                // 1 / |Omega|
   const LdsU32 *pix_lds;     // the first kLdsPix pixels (u | v << 16), staged in LDS
+  const LdsRing *ring;       // ring neighbours 0..7
+  LdsViewConst *vc;          // constants of up to kViewsPerPass neighbour views
+  LdsBest *best;             // plane of the running winner
   double rsx, rsy, rsz;      // K_r^-1 (c_s, 1)
   float4 Cs;                 // mean colour
   float omega_min;           // min over ring neighbours of omega(C_s, C_j); 1 without neighbours
   int M;                     // number of non-empty ring neighbours
-  // lane j < 8: ring neighbour j
-  int ring_cell;             // -1 if outside the grid or empty
-  double rrx, rry, rrz;      // K_r^-1 (c_j, 1)
-  double ring_d;             // centroid depth in state A
-  float ring_w;              // omega(C_s, C_j) scaled by 1 / max_j omega (same ratio in eq. 5)
 };
+
+__device__ __forceinline__ float uni_f(float x) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
 
 __device__ __forceinline__ double bcast_d(double x, int l) {
   const long long b = __double_as_longlong(x);
@@ -771,8 +862,8 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
                           (nx * vw.Kinv_d[2] + ny * vw.Kinv_d[5] + nz * vw.Kinv_d[8]) * idl};
     float acc = 0.f;
     for (int iv = 0; iv < c.N; ++iv) {
-      const PairDev &pg = a.pairs[vw.pair_off + iv];
-      const ViewDev &vi = a.views[pg.i];
+      const PairDev &pg = ro_at(a.pairs, vw.pair_off + iv);
+      const ViewDev &vi = ro_at(a.views, pg.i);
       float H[9];
 #pragma unroll
       for (int r = 0; r < 3; ++r)
@@ -795,15 +886,18 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
   float Es = 1.f;
   if ((a.term_mask & 1u) && c.M > 0) {
     float num = 0.f, den = 0.f;
-    if (lane < 8 && c.ring_cell >= 0) {
-      const double t = nx * c.rrx + ny * c.rry + nz * c.rrz;
-      float sj = 0.f;
-      if (t > 0.0) {
-        const float dd = (float)(c.ring_d - delta / t);
-        sj = __expf(-dd * dd * a.inv2sig2);
+    if (lane < 8) {
+      const RingEntry r = lds_get(c.ring + lane);
+      if (r.cell >= 0) {
+        const double t = nx * r.rx + ny * r.ry + nz * r.rz;
+        float sj = 0.f;
+        if (t > 0.0) {
+          const float dd = (float)(r.d - delta / t);
+          sj = __expf(-dd * dd * a.inv2sig2);
+        }
+        num = r.w * sj;
+        den = r.w;
       }
-      num = c.ring_w * sj;
-      den = c.ring_w;
     }
     Es = ring_sum(num) / ring_sum(den);
   }
@@ -820,8 +914,8 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
   // nearest to the projected centroid, so the FP32 per-sample arithmetic
   // works on small offsets and the nearest-pixel decision of eq. (9) keeps
   // ~1e-6 px accuracy at any image size.  The per-(candidate, view)
-  // constants are composed in FP64 (lane j composes neighbour view j) and
-  // broadcast with readlane.
+  // constants are composed in FP64 (lane j composes neighbour view base + j,
+  // into LDS) and read back into scalar registers view by view.
   float Ec = 1.f;
   if (a.term_mask & 2u) {
     const double idl = 1.0 / delta;
@@ -832,11 +926,13 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
     const float gu = (float)gd0, gv = (float)gd1;
     float sum = 0.f;
     const float tol = 1.f + a.occ_tol;
-    for (int base = 0; base < c.N; base += kWave) {
-      // lane j: constants of neighbour view base + j
-      float ax = 0.f, axu = 0.f, axv = 0.f, ay = 0.f, ayu = 0.f, ayv = 0.f, aw = 0.f, awu = 0.f, awv = 0.f;
-      int X0 = 0, Y0 = 0;
-      if (base + lane < c.N) {
+    const __amdgpu_buffer_rsrc_t px_rs = buffer_rsrc(a.px + c.poff, 8u * (uint32_t)c.A);
+    for (int base = 0; base < c.N; base += kViewsPerPass) {
+      const int nv = min(kViewsPerPass, c.N - base);
+      wave_lds_sync();  // the previous pass's reads are done
+      if (lane < nv) {
+        float ax = 0.f, axu = 0.f, axv = 0.f, ay = 0.f, ayu = 0.f, ayv = 0.f, aw = 0.f, awu = 0.f, awv = 0.f;
+        int X0 = 0, Y0 = 0;
         const PairDev &pg = a.pairs[vw.pair_off + base + lane];
         double H[9];
         const double gg[3] = {gd0, gd1, gd2};
@@ -861,15 +957,18 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         aw = (float)hw;
         awu = (float)H[6];
         awv = (float)H[7];
+        lds_put(c.vc + lane, ViewConst{ax, axu, axv, ay, ayu, ayv, aw, awu, awv, X0, Y0, 0});
       }
-      const int nv = min(kWave, c.N - base);
+      wave_lds_sync();
       for (int jv = 0; jv < nv; ++jv) {
-        // view jv's constants, uniform over the wave
-        const float cax = bcast(ax, jv), caxu = bcast(axu, jv), caxv = bcast(axv, jv);
-        const float cay = bcast(ay, jv), cayu = bcast(ayu, jv), cayv = bcast(ayv, jv);
-        const float caw = bcast(aw, jv), cawu = bcast(awu, jv), cawv = bcast(awv, jv);
-        const float fX0 = (float)__builtin_amdgcn_readlane(X0, jv), fY0 = (float)__builtin_amdgcn_readlane(Y0, jv);
-        const ViewDev &vi = a.views[a.pairs[vw.pair_off + base + jv].i];
+        // view base + jv's constants, uniform over the wave
+        const ViewConst q = lds_get(c.vc + jv);
+        const float cax = uni_f(q.ax), caxu = uni_f(q.axu), caxv = uni_f(q.axv);
+        const float cay = uni_f(q.ay), cayu = uni_f(q.ayu), cayv = uni_f(q.ayv);
+        const float caw = uni_f(q.aw), cawu = uni_f(q.awu), cawv = uni_f(q.awv);
+        const float fX0 = (float)__builtin_amdgcn_readfirstlane(q.X0);
+        const float fY0 = (float)__builtin_amdgcn_readfirstlane(q.Y0);
+        const ViewDev &vi = ro_at(a.views, ro_at(a.pairs, vw.pair_off + base + jv).i);
         const float Wm1 = (float)(vi.W - 1), Hm1 = (float)(vi.H - 1);
         const uint32_t Wv = (uint32_t)vi.W;
         // 16-bit labels when every view has at most 65536 cells: half the
@@ -953,7 +1052,8 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
             for (int k = 0; k < kChains; ++k) accumulate(q[k], C[k], G[k]);
           }
           for (; p < n_lds; p += kWave) one(c.pix_lds[p], narrow);
-          for (p = kLdsPix + lane; p < c.A; p += kWave) one(a.px[c.poff + p].x, narrow);
+          for (p = kLdsPix + lane; p < c.A; p += kWave)
+            one((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(px_rs, (int)(8u * (uint32_t)p), 0, 0), narrow);
         };
         if (a.lab16)
           samples(std::true_type{});
@@ -988,7 +1088,7 @@ __device__ __forceinline__ void ray_of(const ViewDev &vw, double2 cp, double &x,
 // One candidate plane n . X = delta of camera r, its depth d at the
 // superpixel's centroid and its slot number.
 struct Cand {
-  double nx, ny, nz, delta, d;
+  double nx, ny, nz, delta;
   int slot, pad;
 };
 constexpr int kCandBatch = kWave;  // candidates generated per batch (one per lane)
@@ -999,12 +1099,6 @@ __device__ __forceinline__ double uni_d(double x) {
   const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
   const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// Makes earlier LDS writes of any lane of this wave visible to its later reads.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
 }
 
 // Appends this lane's candidate (if valid) to list[base..] keeping lane
@@ -1026,11 +1120,10 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
     cd.ny = uni_d(cd.ny);
     cd.nz = uni_d(cd.nz);
     cd.delta = uni_d(cd.delta);
-    cd.d = uni_d(cd.d);
     cd.slot = __builtin_amdgcn_readfirstlane(cd.slot);
     bool pruned;
     int views;
-    const float E = energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta, b.second, pruned, views);
+    const float E = uni_f(energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta, b.second, pruned, views));
     ++b.evaluated;
     b.view_samples += views;
     if (pruned) {  // bounded below the second best: no change
@@ -1041,11 +1134,11 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
       if (b.slot >= 0) b.second = b.E;
       b.E = E;
       b.slot = cd.slot;
-      b.d = cd.d;
-      b.nx = cd.nx;
-      b.ny = cd.ny;
-      b.nz = cd.nz;
-      b.delta = cd.delta;
+      c.best->nx = cd.nx;
+      c.best->ny = cd.ny;
+      c.best->nz = cd.nz;
+      c.best->delta = cd.delta;
+      c.best->d = cd.delta / (cd.nx * c.rsx + cd.ny * c.rsy + cd.nz * c.rsz);  // depth at the centroid
     } else if (E > b.second) {
       b.second = E;
     }
@@ -1056,15 +1149,26 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
 // kernel, then 8 triangle normals pivoting at the winner's centroid depth.
 // Candidates are generated lane-parallel in slot order into an LDS list and
 // evaluated in that order by one energy loop.
+// The LDS space of one wave in the refinement.
+struct WaveLds {
+  Cand list[kCandBatch];
+  uint32_t pix[kLdsPix];
+  ViewConst vc[kViewsPerPass];
+  RingEntry ring[8];
+  BestPlane best;
+};
+
 template <int FMT>
-__device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand *list, uint32_t *pix_lds) {
+__device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, WaveLds &wl) {
+  Cand *list = wl.list;
+  uint32_t *pix_lds = wl.pix;
   const int lane = threadIdx.x & (kWave - 1);
   SpCtx c;
   c.g = g;
-  c.v = a.sp_view[g];
-  const ViewDev &vw = a.views[c.v];
+  c.v = ro_at(a.sp_view, g);
+  const ViewDev &vw = ro_at(a.views, c.v);
   c.s = g - vw.sp_off;
-  c.A = a.area[g];
+  c.A = ro_at(a.area, g);
   if (c.A == 0) {
     if (lane == 0) {
       a.planesB[g] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1077,22 +1181,21 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
     return;
   }
   c.N = vw.n_pairs;
-  c.poff = a.px_off[g];
+  c.poff = ro_at(a.px_off, g);
   c.invA = 1.f / (float)c.A;
   for (int p = lane; p < min(c.A, kLdsPix); p += kWave) pix_lds[p] = a.px[c.poff + p].x;
   c.pix_lds = (const LdsU32 *)pix_lds;
   wave_lds_sync();
-  const double2 cs = a.centroid_d[g];
+  const double2 cs = ro_at(a.centroid_d, g);
   ray_of(vw, cs, c.rsx, c.rsy, c.rsz);
-  c.Cs = a.colour[g];
+  c.Cs = ro_at(a.colour, g);
   c.ub = (int)floor(cs.x + 0.5);
   c.vb = (int)floor(cs.y + 0.5);
   const int gx = c.s % vw.gw, gy = c.s / vw.gw;
 
-  // ring neighbour j on lane j
-  c.ring_cell = -1;
-  c.rrx = c.rry = c.rrz = 0.0;
-  c.ring_d = 0.0;
+  // ring neighbour j on lane j, then into LDS
+  int ring_cell = -1;
+  double rrx = 0.0, rry = 0.0, rrz = 0.0, ring_d = 0.0;
   float dist2 = INFINITY;
   if (lane < 8) {
     const int x = gx + ring_dx(lane), y = gy + ring_dy(lane);
@@ -1100,20 +1203,26 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
       const int k = y * vw.gw + x;
       const int gk = vw.sp_off + k;
       if (a.area[gk] > 0) {
-        c.ring_cell = k;
-        ray_of(vw, a.centroid_d[gk], c.rrx, c.rry, c.rrz);
-        c.ring_d = a.planesA[gk].x;
+        ring_cell = k;
+        ray_of(vw, a.centroid_d[gk], rrx, rry, rrz);
+        ring_d = a.planesA[gk].x;
         const float4 Ck = a.colour[gk];
         const float dr = c.Cs.x - Ck.x, dg = c.Cs.y - Ck.y, db = c.Cs.z - Ck.z;
         dist2 = dr * dr + dg * dg + db * db;
       }
     }
   }
-  c.M = __popcll(__ballot(c.ring_cell >= 0));
+  c.M = __popcll(__ballot(ring_cell >= 0));
   const float dmin2 = ring_min(dist2);
-  const float dmax2 = ring_max(c.ring_cell >= 0 ? dist2 : -INFINITY);
-  c.ring_w = c.ring_cell >= 0 ? __expf(-(dist2 - dmin2) * a.inv2alpha2) : 0.f;
+  const float dmax2 = ring_max(ring_cell >= 0 ? dist2 : -INFINITY);
+  const float ring_w = ring_cell >= 0 ? __expf(-(dist2 - dmin2) * a.inv2alpha2) : 0.f;
   c.omega_min = c.M > 0 ? __expf(-dmax2 * a.inv2alpha2) : 1.f;
+  LdsRing *ring = (LdsRing *)wl.ring;
+  if (lane < 8) lds_put(ring + lane, RingEntry{rrx, rry, rrz, ring_d, ring_w, ring_cell});
+  c.ring = ring;
+  c.vc = (LdsViewConst *)wl.vc;
+  c.best = (LdsBest *)&wl.best;
+  wave_lds_sync();
 
   Best b;
   b.E = -INFINITY;
@@ -1122,7 +1231,6 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
   b.evaluated = 0;
   b.pruned = 0;
   b.view_samples = 0;
-  b.d = b.nx = b.ny = b.nz = b.delta = 0.0;
 
   // Propagation (Sec. III-C, eq. 4): slot r = 0 the current plane, 1 + j ring
   // neighbour j, 9 + 8 (m / step - 1) + j the cell m cells away along ring
@@ -1159,7 +1267,6 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
           cd.delta = (double)pk.x * (cd.nx * rx + cd.ny * ry + cd.nz * rz);
           const double tt = cd.nx * c.rsx + cd.ny * c.rsy + cd.nz * c.rsz;
           valid = tt > 0.0 && cd.delta > 0.0;
-          cd.d = cd.delta / tt;
         }
       }
     }
@@ -1173,18 +1280,22 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
   // (the winner's centroid depth) and the 3D centroids of ring neighbours j
   // and j+1 at their depths in the state, in FP64.
   if (b.slot >= 0) {
-    const int j2 = (lane + 1) & 7;
-    const int kb = __shfl(c.ring_cell, j2, kWave);
-    const double dbb = __shfl(c.ring_d, j2, kWave);
-    const double rbx = __shfl(c.rrx, j2, kWave), rby = __shfl(c.rry, j2, kWave), rbz = __shfl(c.rrz, j2, kWave);
     bool valid = false;
     Cand cd;
     cd.slot = 1000 + lane;
     cd.pad = 0;
-    cd.nx = cd.ny = cd.nz = cd.delta = cd.d = 0.0;
-    if (lane < 8 && c.ring_cell >= 0 && kb >= 0) {
-      const double Xs0 = b.d * c.rsx, Xs1 = b.d * c.rsy, Xs2 = b.d * c.rsz;
-      const double ea0 = c.ring_d * c.rrx - Xs0, ea1 = c.ring_d * c.rry - Xs1, ea2 = c.ring_d * c.rrz - Xs2;
+    cd.nx = cd.ny = cd.nz = cd.delta = 0.0;
+    RingEntry ra, rb;
+    ra.cell = rb.cell = -1;
+    if (lane < 8) {
+      ra = lds_get(c.ring + lane);
+      rb = lds_get(c.ring + ((lane + 1) & 7));
+    }
+    if (lane < 8 && ra.cell >= 0 && rb.cell >= 0) {
+      const double dbb = rb.d, rbx = rb.rx, rby = rb.ry, rbz = rb.rz;
+      const double bd = c.best->d;
+      const double Xs0 = bd * c.rsx, Xs1 = bd * c.rsy, Xs2 = bd * c.rsz;
+      const double ea0 = ra.d * ra.rx - Xs0, ea1 = ra.d * ra.ry - Xs1, ea2 = ra.d * ra.rz - Xs2;
       const double eb0 = dbb * rbx - Xs0, eb1 = dbb * rby - Xs1, eb2 = dbb * rbz - Xs2;
       double n0 = ea1 * eb2 - ea2 * eb1;
       double n1 = ea2 * eb0 - ea0 * eb2;
@@ -1207,7 +1318,6 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
         cd.nz = n2;
         cd.delta = n0 * Xs0 + n1 * Xs1 + n2 * Xs2;
         valid = tt > 0.0 && cd.delta > 0.0;
-        cd.d = cd.delta / tt;
       }
     }
     const int n = append_cand(list, 0, valid, cd);
@@ -1224,12 +1334,13 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
       a.choice[g] = -1;
       a.margin[g] = 0.f;
     } else {
-      a.planesB[g] = make_float4((float)b.d, (float)b.nx, (float)b.ny, (float)b.nz);
-      const double id = 1.0 / b.delta;
+      const double bnx = c.best->nx, bny = c.best->ny, bnz = c.best->nz;
+      a.planesB[g] = make_float4((float)c.best->d, (float)bnx, (float)bny, (float)bnz);
+      const double id = 1.0 / c.best->delta;
       a.tabB[2 * g] = c.Cs;
-      a.tabB[2 * g + 1] = make_float4((float)((b.nx * vw.Kinv_d[0] + b.ny * vw.Kinv_d[3] + b.nz * vw.Kinv_d[6]) * id),
-                                      (float)((b.nx * vw.Kinv_d[1] + b.ny * vw.Kinv_d[4] + b.nz * vw.Kinv_d[7]) * id),
-                                      (float)((b.nx * vw.Kinv_d[2] + b.ny * vw.Kinv_d[5] + b.nz * vw.Kinv_d[8]) * id),
+      a.tabB[2 * g + 1] = make_float4((float)((bnx * vw.Kinv_d[0] + bny * vw.Kinv_d[3] + bnz * vw.Kinv_d[6]) * id),
+                                      (float)((bnx * vw.Kinv_d[1] + bny * vw.Kinv_d[4] + bnz * vw.Kinv_d[7]) * id),
+                                      (float)((bnx * vw.Kinv_d[2] + bny * vw.Kinv_d[5] + bnz * vw.Kinv_d[8]) * id),
                                       0.f);
       a.energy[g] = b.E;
       a.choice[g] = b.slot;
@@ -1241,16 +1352,18 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Cand
   }
 }
 
+// Five waves per SIMD (at most 96 VGPRs): the sample loop waits on dependent
+// gathers, and the extra wave hides more of that latency than the few
+// registers it costs (spilled only around candidate generation).
 template <int FMT>
-__global__ __launch_bounds__(kBlock) void k_refine(RefineArgs a) {
-  __shared__ Cand s_list[kWavesPerBlock][kCandBatch];
-  __shared__ uint32_t s_pix[kWavesPerBlock][kLdsPix];
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_refine(RefineArgs a) {
+  __shared__ WaveLds s_wave[kWavesPerBlock];
   const int wid = threadIdx.x >> 6;
   const int blk = logical_block((a.S + kWavesPerBlock - 1) / kWavesPerBlock);
   if (blk < 0) return;
   const int g = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + wid);
   if (g >= a.S) return;
-  refine_sp<FMT>(a, g, s_list[wid], s_pix[wid]);
+  refine_sp<FMT>(a, g, s_wave[wid]);
 }
 
 hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st) {
@@ -1276,9 +1389,8 @@ __global__ void k_pool_reset(int *counters) {
 typedef const __attribute__((address_space(4))) PoolStage ConstStage;
 
 template <int OP, int FMT, int KC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SLF_OP_REFINE ? 4 : 1))) void k_pool(const PoolStage *__restrict__ stage_ptr, int *__restrict__ counters) {
-  __shared__ Cand s_list[OP == SLF_OP_REFINE ? kWavesPerBlock : 1][kCandBatch];
-  __shared__ uint32_t s_pix[OP == SLF_OP_REFINE ? kWavesPerBlock : 1][kLdsPix];
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SLF_OP_REFINE ? 5 : 1))) void k_pool(const PoolStage *__restrict__ stage_ptr, int *__restrict__ counters) {
+  __shared__ WaveLds s_wave[OP == SLF_OP_REFINE ? kWavesPerBlock : 1];
   // The stage table does not change during the launch: read it through the
   // constant address space, as kernel arguments are, so that its fields are
   // loaded into scalar registers.
@@ -1319,7 +1431,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SL
       } else {
         const int g0 = (item - J.item_begin) * tile;
         const int g1 = min(g0 + tile, J.S);
-        for (int g = g0; g < g1; ++g) refine_sp<FMT>(J.refine, g, s_list[wid], s_pix[wid]);
+        for (int g = g0; g < g1; ++g) refine_sp<FMT>(J.refine, g, s_wave[wid]);
       }
     }
   }

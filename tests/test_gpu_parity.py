@@ -229,6 +229,29 @@ def test_refine_lockstep_random_state():
     _assert_clean(rep, "random-state refine")
 
 
+def test_refine_wide_labels_sampled():
+    """Views of 320 x 240 = 76800 cells: label gathers take the 32-bit path
+    (16-bit labels cover at most 65536 cells), with many labels above 65535."""
+    from lfsynth import random_planes
+
+    _say("refine with 76800-cell views (32-bit label gathers)")
+    w = tiny_custom(640, 480, 320, 240, n_views=2, seed=13, labels="grid", levels=8, iterations=1)
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    rng = np.random.default_rng(5)
+    # tilts up to 20 degrees: every plane faces the camera out to the image
+    # corners, 63 degrees off axis at f = 200 px
+    A64 = parity.round_state(np.concatenate([random_planes(rng, v.gw, v.gh, 2.0, 8.0, max_tilt_deg=20.0)
+                                             for v in w.rig.views]))
+    for v in range(orc.V):
+        ctx.set_planes(v, A64[orc.view_slice(v)])
+    ctx.propagate(1, 1)
+    sample = [(v, int(s)) for v in range(2) for s in rng.integers(0, 76800, 30)]
+    sample += [(v, int(s)) for v in range(2) for s in rng.integers(65536, 76800, 15)]
+    rep = parity.check_refine(orc, ctx, A64, 1, sample=sample)
+    _assert_clean(rep, "wide-label refine")
+
+
 # ------------------------------------------------------------------ a9: depth readout
 
 def test_depth_readout_matches_oracle():
