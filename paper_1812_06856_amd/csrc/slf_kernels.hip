@@ -819,7 +819,8 @@ struct SpCtx {
   int g, v, s, A, N, poff;
   int ub, vb;                // centroid rounded to the nearest pixel
   float invA;                // 1 / |Omega|
-  const LdsU32 *pix_lds;     // the first kLdsPix pixels (u | v << 16), staged in LDS
+  const LdsU32 *pix_lds;     // pixels 0..n_lds-1 as FP16 pairs (u - ub, v - vb), staged in LDS
+  int n_lds;                 // staged pixels (0 if an offset exceeds 2048: FP16 holds integers exactly up to there)
   const LdsRing *ring;       // ring neighbours 0..7
   LdsViewConst *vc;          // constants of up to kViewsPerPass neighbour views
   LdsBest *best;             // plane of the running winner
@@ -989,9 +990,10 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           bool seen;
           uint32_t pix;
         };
-        auto project = [&](uint32_t uv) {
+        // (du, dv): the pixel relative to (ub, vb).  The staged FP16 offsets
+        // enter the FMAs as mixed-precision operands, converted exactly.
+        auto project = [&](float du, float dv) {
           Proj q;
-          const float du = (float)((int)(uv & 0xffffu) - c.ub), dv = (float)((int)(uv >> 16) - c.vb);
           q.iota = fmaf(gu, du, fmaf(gv, dv, i0));  // 1 / D(p)
           q.w = fmaf(cawu, du, fmaf(cawv, dv, caw));  // z_i(P) = w / iota
           const float rw = rcp(q.w);
@@ -1025,22 +1027,35 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           gx += (q.seen & vis & front) ? gk : 0.f;
           anyY |= q.seen & !vis;
         };
-        auto one = [&](uint32_t uv, auto narrow) {
-          const Proj q = project(uv);
+        auto staged = [&](int p) {
+          const __half2 h = __builtin_bit_cast(__half2, (uint32_t)c.pix_lds[p]);
+          return project(__low2float(h), __high2float(h));
+        };
+        auto listed = [&](int p) {
+          const uint32_t uv = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(px_rs, (int)(8u * (uint32_t)p), 0, 0);
+          return project((float)((int)(uv & 0xffffu) - c.ub), (float)((int)(uv >> 16) - c.vb));
+        };
+        auto one = [&](int p, auto narrow) {
+          const Proj q = listed(p);
           const uint32_t l = label(q, narrow);
           accumulate(q, load_f3(tab_rs, (int)(32u * l)), load_f3(tab_rs, (int)(32u * l + 16u)));
         };
         // kChains pixels per lane per pass keep that many gather chains in
-        // flight; each lane still accumulates its pixels in order.
+        // flight; each lane still accumulates its pixels in order.  A chain
+        // past the last staged pixel re-reads the lane's first one and counts
+        // nothing, so every lane makes the same number of passes.
         auto samples = [&](auto narrow) {
-          const int n_lds = min(c.A, kLdsPix);
-          int p = lane;
-          for (; p + (kChains - 1) * kWave < n_lds; p += kChains * kWave) {
+          const int n_lds = c.n_lds;
+          for (int p = lane; p < n_lds; p += kChains * kWave) {
             Proj q[kChains];
             uint32_t l[kChains];
             float3 C[kChains], G[kChains];
 #pragma unroll
-            for (int k = 0; k < kChains; ++k) q[k] = project(c.pix_lds[p + k * kWave]);
+            for (int k = 0; k < kChains; ++k) {
+              const bool in = k == 0 || p + k * kWave < n_lds;
+              q[k] = staged(in ? p + k * kWave : p);
+              q[k].seen &= in;
+            }
 #pragma unroll
             for (int k = 0; k < kChains; ++k) l[k] = label(q[k], narrow);
 #pragma unroll
@@ -1051,9 +1066,7 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
 #pragma unroll
             for (int k = 0; k < kChains; ++k) accumulate(q[k], C[k], G[k]);
           }
-          for (; p < n_lds; p += kWave) one(c.pix_lds[p], narrow);
-          for (p = kLdsPix + lane; p < c.A; p += kWave)
-            one((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(px_rs, (int)(8u * (uint32_t)p), 0, 0), narrow);
+          for (int p = n_lds + lane; p < c.A; p += kWave) one(p, narrow);
         };
         if (a.lab16)
           samples(std::true_type{});
@@ -1183,14 +1196,21 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Wave
   c.N = vw.n_pairs;
   c.poff = ro_at(a.px_off, g);
   c.invA = 1.f / (float)c.A;
-  for (int p = lane; p < min(c.A, kLdsPix); p += kWave) pix_lds[p] = a.px[c.poff + p].x;
-  c.pix_lds = (const LdsU32 *)pix_lds;
-  wave_lds_sync();
   const double2 cs = ro_at(a.centroid_d, g);
   ray_of(vw, cs, c.rsx, c.rsy, c.rsz);
   c.Cs = ro_at(a.colour, g);
   c.ub = (int)floor(cs.x + 0.5);
   c.vb = (int)floor(cs.y + 0.5);
+  bool fits = true;
+  for (int p = lane; p < min(c.A, kLdsPix); p += kWave) {
+    const uint32_t uv = a.px[c.poff + p].x;
+    const int du = (int)(uv & 0xffffu) - c.ub, dv = (int)(uv >> 16) - c.vb;
+    fits = fits && abs(du) <= 2048 && abs(dv) <= 2048;
+    pix_lds[p] = __builtin_bit_cast(uint32_t, __floats2half2_rn((float)du, (float)dv));
+  }
+  c.n_lds = __ballot(!fits) == 0ull ? min(c.A, kLdsPix) : 0;
+  c.pix_lds = (const LdsU32 *)pix_lds;
+  wave_lds_sync();
   const int gx = c.s % vw.gw, gy = c.s / vw.gw;
 
   // ring neighbour j on lane j, then into LDS
