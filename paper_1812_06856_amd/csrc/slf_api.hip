@@ -344,6 +344,7 @@ void slf::sweep_args(const slf_ctx *c, SweepArgs &a) {
   a.area = c->d_area;
   a.px_off = c->d_px_off;
   a.px = c->d_px;
+  a.bbox = c->d_bbox;
   a.quads = c->d_quads;
   a.quad_bytes = (uint32_t)c->quads_bytes;
   a.S = c->S;

@@ -52,6 +52,7 @@ struct SweepArgs {
   const int *area;
   const int *px_off;
   const PixEntry *px;
+  const int4 *bbox;     // per superpixel pixel bounding box (x0, y0, x1, y1)
   const void *quads;
   uint32_t quad_bytes;  // bytes of texels over all views (< 4 GiB)
   int S;

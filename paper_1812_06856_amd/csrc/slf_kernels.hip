@@ -121,15 +121,26 @@ __device__ __forceinline__ float bcast(float x, int l) {
 }
 
 // ------------------------------------------------------------------ image texels
-// A texel (x0, y0), x0 in [0, W-1], y0 in [0, H-1], holds the four bilinear
-// taps (x0,y0), (x0+1,y0), (x0,y0+1), (x0+1,y0+1), with the last column and
-// row replicated, so one aligned load fetches a whole bilinear footprint.
-
-// Texels: per view a (W+1) x (H+1) RGBA image (last column and row
-// replicated), 4 / 8 / 16 bytes per texel for RGBA8 / FP16 / FP32.
-size_t quad_bytes(int fmt) { return fmt == SLF_FMT_F32 ? 16 : fmt == SLF_FMT_F16 ? 8 : 4; }
+// Per view (W+1) x (H+1) entries, entry (x, y) at index y (W+1) + x, the last
+// column and row replicated.  FP16 / FP32: the entry is the RGBA texel
+// (x, y), 8 / 16 bytes, and a bilinear footprint takes one load per row.
+// RGBA8: the entry is the texel pair (x, y), (x, y+1), 8 bytes, so entries
+// (x0, y0) and (x0+1, y0), 16 contiguous bytes, hold all four taps and a
+// sample takes a single load (the address path, not the bytes, limits the
+// sweep's gathers).
+size_t quad_bytes(int fmt) { return fmt == SLF_FMT_F32 ? 16 : 8; }
 template <int FMT>
-constexpr int kQuadBytes = FMT == SLF_FMT_F32 ? 16 : FMT == SLF_FMT_F16 ? 8 : 4;
+constexpr int kQuadBytes = FMT == SLF_FMT_F32 ? 16 : 8;
+
+// An entry of a table that no kernel writes while it reads it (geometry,
+// superpixel statistics, the state being read), accessed through the
+// constant address space: at a wave-uniform index the compiler then always
+// emits a scalar load, whatever it can prove about the stores around it.
+template <class T>
+__device__ __forceinline__ const T &ro_at(const T *p, int64_t i) {
+  typedef const __attribute__((address_space(4))) T CT;
+  return *(const T *)&((CT *)p)[i];
+}
 
 // Raw buffer resource over `bytes` bytes at p (gfx9-family descriptor word 3):
 // loads past the end return 0.
@@ -139,9 +150,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, uin
 
 __device__ __forceinline__ uint4 load_u4(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
-}
-__device__ __forceinline__ uint2 load_u2(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
-  return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
 }
 
 // The four bilinear taps (x0, y0), (x0+1, y0), (x0, y0+1), (x0+1, y0+1) as
@@ -153,8 +161,8 @@ __device__ __forceinline__ void fetch_quad(__amdgpu_buffer_rsrc_t rs, uint32_t o
 template <>
 __device__ __forceinline__ void fetch_quad<SLF_FMT_U8>(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t row,
                                                        float (&t)[12]) {
-  const uint2 a = load_u2(rs, off), b = load_u2(rs, off + row);
-  const uint32_t w[4] = {a.x, a.y, b.x, b.y};
+  const uint4 q = load_u4(rs, off);  // (x0, y0), (x0, y0+1), (x0+1, y0), (x0+1, y0+1)
+  const uint32_t w[4] = {q.x, q.z, q.y, q.w};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     t[3 * j + 0] = (float)(w[j] & 255u);
@@ -197,10 +205,14 @@ __global__ __launch_bounds__(256) void k_quads(const uint8_t *rgb, int W, int H,
   const int64_t n = (int64_t)Wp * (H + 1);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n) return;
-  const int x = min((int)(idx % Wp), W - 1), y = min((int)(idx / Wp), H - 1);  // replicated edge
+  const int yr = (int)(idx / Wp);
+  const int x = min((int)(idx % Wp), W - 1), y = min(yr, H - 1);  // replicated edge
   const uint8_t *c = rgb + 3 * ((int64_t)y * W + x);
   if (fmt == SLF_FMT_U8) {
-    static_cast<uint32_t *>(quads)[quad_off + idx] = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
+    const uint8_t *d = rgb + 3 * ((int64_t)min(yr + 1, H - 1) * W + x);  // the texel below
+    static_cast<uint2 *>(quads)[quad_off + idx] =
+        make_uint2((uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16),
+                   (uint32_t)d[0] | ((uint32_t)d[1] << 8) | ((uint32_t)d[2] << 16));
   } else if (fmt == SLF_FMT_F16) {
     __half2 rg = __floats2half2_rn((float)c[0], (float)c[1]);
     __half2 ba = __floats2half2_rn((float)c[2], 0.f);
@@ -411,23 +423,30 @@ hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V
 // Samples behind the camera or outside [0, W-1] x [0, H-1] cost T.  The texel
 // address is clamped into the image whatever the coordinates, so the load is
 // always in bounds and issued unconditionally.
+//
+// With check = false the caller guarantees w > 0 and a position inside the
+// image (see sweep_levels): the clamp would be the identity, so it and the
+// test are skipped and the result is the same.
 template <int FMT>
 __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm1, float Hm1, int Wi, int Hi,
                                              __amdgpu_buffer_rsrc_t quads, uint32_t vbase, float r0, float g0,
-                                             float b0, float T) {
+                                             float b0, float T, bool check = true) {
   const float rw = rcp(w);
   const float xs = x * rw, ys = y * rw;
   // Clamp into the image; the sample counts only if unclamped (a NaN fails
   // the equality, and converts to texel 0, so the load stays in bounds).
-  const float xc = __builtin_amdgcn_fmed3f(xs, 0.f, Wm1), yc = __builtin_amdgcn_fmed3f(ys, 0.f, Hm1);
-  const bool in = (w > 0.f) & (xc == xs) & (yc == ys);
+  const float xc = check ? __builtin_amdgcn_fmed3f(xs, 0.f, Wm1) : xs;
+  const float yc = check ? __builtin_amdgcn_fmed3f(ys, 0.f, Hm1) : ys;
+  const bool in = !check || ((w > 0.f) & (xc == xs) & (yc == ys));
   // Taps at floor(x) and floor(x)+1 with weight fract(x); at x = W-1 the
   // replicated column has weight 0, which equals clamping the left tap to W-2.
   const int x0 = (int)xc, y0 = (int)yc;
   const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
   float t[12];
   const uint32_t row = (uint32_t)(Wi + 1) * (uint32_t)kQuadBytes<FMT>;
-  fetch_quad<FMT>(quads, vbase + (uint32_t)(y0 * (Wi + 1) + x0) * (uint32_t)kQuadBytes<FMT>, row, t);
+  // image sides are below 2^16, so 24-bit multiplies (full rate) form the texel index
+  fetch_quad<FMT>(quads, vbase + (__umul24((uint32_t)y0, (uint32_t)(Wi + 1)) + (uint32_t)x0) * (uint32_t)kQuadBytes<FMT>,
+                  row, t);
   // bilinear weights of the four taps (FP16 taps feed mixed-precision FMAs directly)
   const float ofx = 1.f - fx, ofy = 1.f - fy;
   const float w00 = ofx * ofy, w10 = fx * ofy, w01 = ofx * fy, w11 = fx * fy;
@@ -445,14 +464,15 @@ __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm
 template <>
 __device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, float w, float Wm1, float Hm1, int Wi,
                                                           int Hi, __amdgpu_buffer_rsrc_t quads, uint32_t vbase,
-                                                          float r0, float g0, float b0, float T) {
+                                                          float r0, float g0, float b0, float T, bool check) {
   const float rw = rcp(w);
   const float xs = x * rw, ys = y * rw;
-  const float xc = __builtin_amdgcn_fmed3f(xs, 0.f, Wm1), yc = __builtin_amdgcn_fmed3f(ys, 0.f, Hm1);
-  const bool in = (w > 0.f) & (xc == xs) & (yc == ys);
+  const float xc = check ? __builtin_amdgcn_fmed3f(xs, 0.f, Wm1) : xs;
+  const float yc = check ? __builtin_amdgcn_fmed3f(ys, 0.f, Hm1) : ys;
+  const bool in = !check || ((w > 0.f) & (xc == xs) & (yc == ys));
   const int x0 = (int)xc, y0 = (int)yc;
   const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
-  const uint32_t off = vbase + (uint32_t)(y0 * (Wi + 1) + x0) * 8u;
+  const uint32_t off = vbase + (__umul24((uint32_t)y0, (uint32_t)(Wi + 1)) + (uint32_t)x0) * 8u;
   const uint4 lo = load_u4(quads, off), hi = load_u4(quads, off + (uint32_t)(Wi + 1) * 8u);
   typedef _Float16 h2 __attribute__((ext_vector_type(2)));
   const h2 rg00 = __builtin_bit_cast(h2, lo.x), b00 = __builtin_bit_cast(h2, lo.y);
@@ -521,10 +541,36 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
   const int N = vw.n_pairs;
   const int P = A * N;
   const int poff = a.px_off[g];
+  const int4 bb = ro_at(a.bbox, g);  // pixel bounding box (x0, y0, x1, y1)
   for (int k0 = k_begin; k0 < k_end; k0 += KC) {
     float q[KC];
 #pragma unroll
     for (int j = 0; j < KC; ++j) q[j] = (float)level_q(a.seed, a.jitter, a.qmin, a.dq, v, s, k0 + j);
+    // Lane j < N: does every sample of neighbour view j at this chunk's
+    // levels land inside the image, at least half a pixel from its border,
+    // with w > 0?  x, y, w are affine in the pixel for fixed q and in q for
+    // fixed pixel, and every level of the chunk (also one past `levels`)
+    // has q in [q_min + k0 dq, q_min + (k0 + KC) dq]: so w is smallest, and
+    // the image positions (a projective map of the box, moving monotonically
+    // along epipolar lines as q changes) are extreme, at the 8 corners of
+    // box x q-range.  The half-pixel margin is far above FP32 rounding.
+    bool inner = false;
+    if (lane < N) {
+      const PairDev &pg = a.pairs[vw.pair_off + lane];
+      const ViewDev &vi = a.views[pg.i];
+      const float qlo = (float)(a.qmin + (double)k0 * a.dq), qhi = (float)(a.qmin + (double)(k0 + KC) * a.dq);
+      const float xmax = (float)vi.W - 1.5f, ymax = (float)vi.H - 1.5f;
+      inner = true;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const float cu = (float)((c & 1) ? bb.z : bb.x), cv = (float)((c & 2) ? bb.w : bb.y), cq = (c & 4) ? qhi : qlo;
+        const float cx = fmaf(cq, pg.b[0], fmaf(pg.A[0], cu, fmaf(pg.A[1], cv, pg.A[2])));
+        const float cy = fmaf(cq, pg.b[1], fmaf(pg.A[3], cu, fmaf(pg.A[4], cv, pg.A[5])));
+        const float cw = fmaf(cq, pg.b[2], fmaf(pg.A[6], cu, fmaf(pg.A[7], cv, pg.A[8])));
+        inner = inner && cw > 1e-3f && cx >= 0.5f * cw && cx <= xmax * cw && cy >= 0.5f * cw && cy <= ymax * cw;
+      }
+    }
+    const uint64_t inner_views = __ballot(inner);
     float acc[KC];
 #pragma unroll
     for (int j = 0; j < KC; ++j) acc[j] = 0.f;
@@ -560,10 +606,17 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
       const float ax = fmaf(A0, pu, fmaf(A1, pv, A2));
       const float ay = fmaf(A3, pu, fmaf(A4, pv, A5));
       const float aw = fmaf(A6, pu, fmaf(A7, pv, A8));
+      // every active lane in an inner view: samples without the bounds test
+      if (__ballot(((inner_views >> iv) & 1ull) == 0ull) == 0ull) {
 #pragma unroll
-      for (int kk = 0; kk < KC; ++kk) {
-        acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi,
-                                    Hi, qrs, qbase, r0, g0, b0, a.T255);
+        for (int kk = 0; kk < KC; ++kk)
+          acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi,
+                                      Hi, qrs, qbase, r0, g0, b0, a.T255, false);
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk)
+          acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi,
+                                      Hi, qrs, qbase, r0, g0, b0, a.T255, true);
       }
       p += kWave;
       while (p >= A) {
@@ -708,16 +761,6 @@ constexpr int kLdsPix = 1024;  // pixels of a superpixel staged in LDS (the rest
 #define SLF_REFINE_CHAINS 2
 #endif
 constexpr int kChains = SLF_REFINE_CHAINS;  // independent gather chains per lane in the energy loop
-
-// An entry of a table that no kernel writes while it reads it (geometry,
-// superpixel statistics, the state being read), accessed through the
-// constant address space: at a wave-uniform index the compiler then always
-// emits a scalar load, whatever it can prove about the stores around it.
-template <class T>
-__device__ __forceinline__ const T &ro_at(const T *p, int64_t i) {
-  typedef const __attribute__((address_space(4))) T CT;
-  return *(const T *)&((CT *)p)[i];
-}
 
 typedef __attribute__((address_space(3))) uint32_t LdsU32;
 
@@ -1003,7 +1046,7 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           // clamp into the image (a NaN fails the equality and converts to 0)
           const float uc = __builtin_amdgcn_fmed3f(uf, 0.f, Wm1), vc = __builtin_amdgcn_fmed3f(vf, 0.f, Hm1);
           q.seen = (q.iota > 0.f) & (q.w > 0.f) & (uc == uf) & (vc == vf);
-          q.pix = (uint32_t)(int)vc * Wv + (uint32_t)(int)uc;
+          q.pix = __umul24((uint32_t)(int)vc, Wv) + (uint32_t)(int)uc;  // sides below 2^16
           return q;
         };
         auto label = [&](const Proj &q, auto narrow) -> uint32_t {
