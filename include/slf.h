@@ -120,7 +120,10 @@ int slf_set_labels(slf_ctx *ctx, int view, const int32_t *labels, int64_t row_st
  * current images and labels.  slf_sweep, slf_set_planes and slf_propagate do
  * this themselves when inputs changed; calling it first separates the setup
  * from the sweep.  Synchronises (label range errors surface here as
- * SLF_EINVAL).  SLF_ESTATE unless cameras, images and labels are set. */
+ * SLF_EINVAL).  SLF_ESTATE unless cameras, images and labels are set;
+ * SLF_EUNSUPPORTED if the image texels of all views would exceed 4 GiB
+ * ((W+1)(H+1) entries per view of 8 bytes for SLF_IMAGE_U8 and
+ * SLF_IMAGE_F16, 16 bytes for SLF_IMAGE_F32). */
 int slf_prepare(slf_ctx *ctx);
 /* Plane sweep (Sec. III-B) over all superpixels of all views: builds the
  * superpixel pixel lists and statistics if images or labels changed, then for

@@ -260,7 +260,8 @@ int slf::ensure_setup(slf_ctx *c) {
     const size_t need = (size_t)texels * quad_bytes(fmt);
     // one 32-bit buffer resource covers every view's texels
     if (need > 0xFFFFFFF0ull)
-      return c->fail(SLF_EUNSUPPORTED, "texel storage of %zu bytes exceeds 4 GiB; use a smaller image precision",
+      return c->fail(SLF_EUNSUPPORTED,
+                     "texel storage of %zu bytes exceeds 4 GiB (8 bytes per pixel for RGBA8 and FP16, 16 for FP32)",
                      need);
     if (need > c->quads_bytes) {
       if (c->d_quads) (void)hipFree(c->d_quads);
