@@ -229,6 +229,23 @@ def test_refine_lockstep_random_state():
     _assert_clean(rep, "random-state refine")
 
 
+def test_refine_lockstep_far_pixels():
+    """4200-px-wide views whose last grid cell also owns the leftmost 100
+    columns: its pixels lie up to 3359 px from its centroid, beyond what the
+    FP16 offsets staged for the projection hold exactly (2048), so it reads
+    every pixel from the list; the other cells are staged, with tails past
+    the staging capacity."""
+    _say("refine lockstep with pixels far from their centroid")
+    w = tiny_custom(4200, 24, 4, 1, n_views=2, seed=17, labels="grid", levels=8, iterations=2)
+    for v in w.rig.views:
+        v.labels[:, :100] = 3
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    ctx.sweep()
+    _assert_clean(parity.check_sweep(orc, ctx), "far-pixel sweep")
+    _lockstep(w, 2, ctx=ctx, orc=orc)
+
+
 def test_refine_wide_labels_sampled():
     """Views of 320 x 240 = 76800 cells: label gathers take the 32-bit path
     (16-bit labels cover at most 65536 cells), with many labels above 65535."""
