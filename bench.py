@@ -220,6 +220,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     evals, samples, pruned = ctx.work_detail()
+    sweep_computed, sweep_total = ctx.sweep_work()
     K = args.steps
 
     def span(a, b):
@@ -230,10 +231,10 @@ def main():
     t_ref = [span("ref%d_0" % it, "ref%d_1" % it) for it in range(1, p.iterations + 1)]
     ms_ref_total = float(np.mean([sum(t_ref[i][k] for i in range(len(t_ref))) for k in range(K)]))
 
-    # per-step algorithmic work
-    area = np.concatenate([ctx.get_superpixels(i)[0] for i in range(V)])
+    # per-step work: px-view samples computed (the sweep's level bound skips
+    # samples of levels that can be neither chosen nor second best)
     n_pairs = V - 1
-    sweep_samples = int(area.sum()) * n_pairs * p.levels
+    sweep_samples = sweep_computed // K
     refine_samples = samples // K - sweep_samples
     sweep_ms = float(np.mean(t_sweep))
     ref_ms = ms_ref_total
@@ -268,6 +269,7 @@ def main():
         "px_view_samples_per_s": samples / dt,
         "evals_per_step": evals // K,
         "refine_candidates_pruned_per_step": pruned // K,
+        "sweep_samples_computed_frac": sweep_computed / max(1, sweep_total),
         "stage_ms": {"setup": float(np.mean(t_setup)), "sweep": sweep_ms, "refine_total": ref_ms,
                      "refine_per_iteration": [float(np.mean(t)) for t in t_ref]},
         "roofline": {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": peak,

@@ -174,8 +174,19 @@ int slf_get_superpixels(slf_ctx *ctx, int view, int32_t *area, float *centroid, 
  * consistency term (views left contributing at most 1 + occlusion weight)
  * lay below the second-best energy so far, so they could change neither
  * the winner nor the margin.  They count in evals; only the samples of the
- * views computed count in samples.  Synchronises. */
+ * views computed count in samples.  Sweep levels are decided the same way
+ * (see slf_get_sweep_work): every level counts in evals, only the samples
+ * computed count in samples.  Synchronises. */
 int slf_get_work(slf_ctx *ctx, uint64_t *evals, uint64_t *samples, uint64_t *pruned);
+/* Sweep work since the last reset; either output may be NULL.  The sweep
+ * (Sec. III-B, eq. 2) scores levels in chunks; each px-view sample costs
+ * >= 0, so a level's partial cost bounds its cost from below, and a chunk
+ * stops once every level in it is bounded above the second-best complete
+ * cost: none of them can be the chosen level or the second best, so plane,
+ * cost, level and margin are those of the full sweep.  computed: px-view
+ * samples the sweeps computed; total: the samples of a sweep without that
+ * bound (pixels x neighbour views x levels).  Synchronises. */
+int slf_get_sweep_work(slf_ctx *ctx, uint64_t *computed, uint64_t *total);
 int slf_reset_work(slf_ctx *ctx);
 /* Waits for all work enqueued by the context. */
 int slf_synchronize(slf_ctx *ctx);

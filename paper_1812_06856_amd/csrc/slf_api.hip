@@ -361,6 +361,7 @@ void slf::sweep_args(const slf_ctx *c, SweepArgs &a) {
   a.cost = c->d_energy;
   a.choice = c->d_choice;
   a.margin = c->d_margin;
+  a.work = c->d_work;
 }
 
 void slf::after_sweep(slf_ctx *c) {
@@ -373,7 +374,7 @@ void slf::after_sweep(slf_ctx *c) {
       px += (uint64_t)A;
     }
     c->host_evals += nonempty * (uint64_t)c->p.levels;
-    c->host_samples += px * (uint64_t)d.n_pairs * (uint64_t)c->p.levels;
+    c->host_sweep_total += px * (uint64_t)d.n_pairs * (uint64_t)c->p.levels;
     c->vh[v].has_planes = true;
   }
 }
@@ -476,8 +477,8 @@ int slf_create(int device_ordinal, slf_ctx **out) {
     return SLF_EDEVICE;
   }
   if (hipMalloc((void **)&c->d_err, sizeof(int)) != hipSuccess ||
-      hipMalloc((void **)&c->d_work, 3 * sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->d_work, 0, 3 * sizeof(unsigned long long)) != hipSuccess) {
+      hipMalloc((void **)&c->d_work, kWorkCounters * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->d_work, 0, kWorkCounters * sizeof(unsigned long long)) != hipSuccess) {
     free_all(c);
     delete c;
     return SLF_ENOMEM;
@@ -830,12 +831,24 @@ int slf_get_work(slf_ctx *c, uint64_t *evals, uint64_t *samples, uint64_t *prune
   if (!c) return SLF_EINVAL;
   if (int rc = check_idle(c)) return rc;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
-  unsigned long long w[3] = {0, 0, 0};
+  unsigned long long w[kWorkCounters] = {0, 0, 0, 0};
   HIP_OR_FAIL(c, hipMemcpyAsync(w, c->d_work, sizeof w, hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   if (evals) *evals = c->host_evals + w[0];
-  if (samples) *samples = c->host_samples + w[1];
+  if (samples) *samples = w[1] + w[3];
   if (pruned) *pruned = w[2];
+  return SLF_OK;
+}
+
+int slf_get_sweep_work(slf_ctx *c, uint64_t *computed, uint64_t *total) {
+  if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  unsigned long long w = 0;
+  HIP_OR_FAIL(c, hipMemcpyAsync(&w, c->d_work + 3, sizeof w, hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (computed) *computed = w;
+  if (total) *total = c->host_sweep_total;
   return SLF_OK;
 }
 
@@ -843,8 +856,8 @@ int slf_reset_work(slf_ctx *c) {
   if (!c) return SLF_EINVAL;
   if (int rc = check_idle(c)) return rc;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
-  HIP_OR_FAIL(c, hipMemsetAsync(c->d_work, 0, 3 * sizeof(unsigned long long), c->stream));
-  c->host_evals = c->host_samples = 0;
+  HIP_OR_FAIL(c, hipMemsetAsync(c->d_work, 0, kWorkCounters * sizeof(unsigned long long), c->stream));
+  c->host_evals = c->host_sweep_total = 0;
   return SLF_OK;
 }
 

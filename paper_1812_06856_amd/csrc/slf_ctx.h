@@ -71,6 +71,8 @@ struct slf_ctx {
   float4 *d_tab[2] = {nullptr, nullptr};  // per superpixel {colour, inverse-depth row}
   float *d_energy = nullptr, *d_margin = nullptr;
   int *d_choice = nullptr;
+  // device work counters: [0] refinement evals, [1] refinement samples,
+  // [2] refinement candidates pruned, [3] sweep samples computed
   unsigned long long *d_work = nullptr;
   float *d_depth_tmp = nullptr;
   int64_t depth_tmp_n = 0;
@@ -78,7 +80,8 @@ struct slf_ctx {
   std::vector<int> area_h;
   std::vector<double2> cen_h;
   std::vector<float4> col_h;
-  uint64_t host_evals = 0, host_samples = 0;
+  uint64_t host_evals = 0;        // sweep hypotheses (levels x non-empty superpixels)
+  uint64_t host_sweep_total = 0;  // sweep px-view samples without the level bound
 
   // Warm start: every view had planes when the superpixels were last rebuilt
   // for new images on the same cameras and grids.

@@ -67,6 +67,7 @@ struct SweepArgs {
   float *cost;         // out
   int *choice;         // out
   float *margin;       // out
+  unsigned long long *work;  // [3] += px-view samples computed (the level bound skips the rest)
 };
 
 struct RefineArgs {
@@ -89,7 +90,7 @@ struct RefineArgs {
   float *energy;
   int *choice;
   float *margin;
-  unsigned long long *work;  // [0] evals, [1] samples
+  unsigned long long *work;  // [0] evals, [1] samples, [2] candidates pruned
   int S;
   int iter;
   int kernel_step;
@@ -113,6 +114,7 @@ struct PoolJob {
 };
 constexpr int kPoolQueues = 8;      // one per XCD
 constexpr int kPoolMaxJobs = 64;    // rigs in one stage
+constexpr int kWorkCounters = 4;      // per-context device work counters (slf_ctx::d_work)
 constexpr int kPoolCounterStride = 16;  // ints between claim counters (one 64-byte line each)
 // A stage: every job runs the same op in the same image format.  Items
 // [qbegin[q], qend[q]) form queue q; the waves of XCD q drain it first.

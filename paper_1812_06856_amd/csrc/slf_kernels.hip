@@ -533,10 +533,22 @@ __host__ __device__ inline int launch_blocks(int nblocks) {
 // ties.
 // Costs of levels [k_begin, k_end) of superpixel g: the smallest (ties: the
 // lowest level) and the second smallest, uniform over the wave.
+// Every kBoundCheck pixel passes, once two levels are complete, the chunk's
+// partial costs are compared with the second-best complete cost.  Each
+// sample costs >= 0, so a partial cost bounds the level's cost from below;
+// when every level of the chunk is bounded above the second best (times
+// kBoundMargin, far above the rounding of the differently ordered partial
+// sums) none of them can be the best or the second best, and the chunk
+// stops.  The levels that finish are summed exactly as without the bound, so
+// the outputs are unchanged.  *computed receives the px-view samples
+// computed for levels below k_end.
+constexpr int kBoundCheck = 4;
+constexpr float kBoundMargin = 1.00001f;
+
 template <int FMT, int KC>
 __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, const int v, const int s,
                                              const ViewDev &vw, const int A, const int k_begin, const int k_end,
-                                             float &best, float &second, int &kbest) {
+                                             float &best, float &second, int &kbest, uint64_t &computed) {
   const int lane = threadIdx.x & (kWave - 1);
   const int N = vw.n_pairs;
   const int P = A * N;
@@ -585,7 +597,10 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
     int Wi = 2, Hi = 2;
     const __amdgpu_buffer_rsrc_t qrs = buffer_rsrc(a.quads, a.quad_bytes);
     uint32_t qbase = 0;
-    for (int j = lane; j < P; j += kWave) {
+    const int n_pass = (P + kWave - 1) / kWave;
+    int passes = n_pass;
+    for (int it = 0; it < n_pass; ++it) {
+      if (lane + it * kWave < P) {
       if (iv != cur) {
         const PairDev &pg = a.pairs[vw.pair_off + iv];
         A0 = pg.A[0]; A1 = pg.A[1]; A2 = pg.A[2];
@@ -623,7 +638,21 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
         p -= A;
         ++iv;
       }
+      }
+      if ((it & (kBoundCheck - 1)) == kBoundCheck - 1 && it + 1 < n_pass && second < INFINITY) {
+        const float lim = second * kBoundMargin;
+        bool bounded = true;
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk)
+          if (bounded && k0 + kk < k_end) bounded = wave_sum(acc[kk]) > lim;
+        if (bounded) {
+          passes = it + 1;
+          break;
+        }
+      }
     }
+    computed += (uint64_t)min(P, passes * kWave) * (uint64_t)min(KC, k_end - k0);
+    if (passes < n_pass) continue;  // no level of this chunk can be best or second best
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       const float C = wave_sum(acc[kk]);
@@ -677,8 +706,12 @@ __device__ __forceinline__ void sweep_sp(const SweepArgs &a, const int g) {
   }
   float best = INFINITY, second = INFINITY;
   int kbest = 0;
-  sweep_levels<FMT, KC>(a, g, v, s, vw, A, 0, a.levels, best, second, kbest);
-  if (lane == 0) sweep_finish(a, g, v, s, A, vw.n_pairs, best, second, kbest);
+  uint64_t computed = 0;
+  sweep_levels<FMT, KC>(a, g, v, s, vw, A, 0, a.levels, best, second, kbest, computed);
+  if (lane == 0) {
+    sweep_finish(a, g, v, s, A, vw.n_pairs, best, second, kbest);
+    atomicAdd(&a.work[3], (unsigned long long)computed);
+  }
 }
 
 // Levels of part `part` of `split` (contiguous, whole level chunks) of
@@ -700,8 +733,12 @@ __device__ __forceinline__ void sweep_part(const SweepArgs &a, const int g, cons
   const int kb = part * per, ke = min(a.levels, kb + per);
   float best = INFINITY, second = INFINITY;
   int kbest = 0;
-  if (kb < ke) sweep_levels<FMT, KC>(a, g, v, s, vw, A, kb, ke, best, second, kbest);
-  if (lane == 0) parts[part] = make_float4(best, second, __int_as_float(kbest), 0.f);
+  uint64_t computed = 0;  // the bound uses this part's own second best, so its two smallest stay exact
+  if (kb < ke) sweep_levels<FMT, KC>(a, g, v, s, vw, A, kb, ke, best, second, kbest, computed);
+  if (lane == 0) {
+    parts[part] = make_float4(best, second, __int_as_float(kbest), 0.f);
+    atomicAdd(&a.work[3], (unsigned long long)computed);
+  }
 }
 
 // Merges the parts of superpixel g in level order: the two smallest costs

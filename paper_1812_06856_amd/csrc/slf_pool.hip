@@ -628,14 +628,15 @@ int slf_pool_autotune(slf_pool *P, int *from_cache) {
     return SLF_OK;
   }
   // work counters and plane state are restored at the end
-  std::vector<unsigned long long> work(3 * P->rigs.size());
+  std::vector<unsigned long long> work(kWorkCounters * P->rigs.size());
   std::vector<uint64_t> hwork(2 * P->rigs.size());
   for (size_t i = 0; i < P->rigs.size(); ++i) {
     slf_ctx *c = P->rigs[i];
-    if (hipMemcpy(&work[3 * i], c->d_work, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(&work[kWorkCounters * i], c->d_work, kWorkCounters * sizeof(unsigned long long),
+                  hipMemcpyDeviceToHost) != hipSuccess)
       return P->fail(SLF_EDEVICE, "work counter read failed");
     hwork[2 * i] = c->host_evals;
-    hwork[2 * i + 1] = c->host_samples;
+    hwork[2 * i + 1] = c->host_sweep_total;
   }
   const int s_cap = 2048;
   slf_pool_config best = P->cfg;
@@ -681,11 +682,12 @@ int slf_pool_autotune(slf_pool *P, int *from_cache) {
   if (hipStreamSynchronize(P->stream) != hipSuccess) return P->fail(SLF_EDEVICE, "hipStreamSynchronize failed");
   for (size_t i = 0; i < P->rigs.size(); ++i) {
     slf_ctx *c = P->rigs[i];
-    if (hipMemcpy(c->d_work, &work[3 * i], 3 * sizeof(unsigned long long), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(c->d_work, &work[kWorkCounters * i], kWorkCounters * sizeof(unsigned long long),
+                  hipMemcpyHostToDevice) != hipSuccess)
       return P->fail(SLF_EDEVICE, "work counter restore failed");
     for (auto &v : c->vh) v.has_planes = true;
     c->host_evals = hwork[2 * i];
-    c->host_samples = hwork[2 * i + 1];
+    c->host_sweep_total = hwork[2 * i + 1];
   }
   P->tuned[key] = best;
   return SLF_OK;

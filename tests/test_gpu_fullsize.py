@@ -88,6 +88,8 @@ def test_fullsize_pipeline_properties(full):
     ev0, sm0 = ctx.work()
     n_nonempty = int((area > 0).sum())
     assert ev0 == n_nonempty * 256
+    computed, total = ctx.sweep_work()
+    assert total == int(area.sum()) * 7 * 256 and 0 < computed <= total and sm0 == computed
     means = []
     for it in range(1, 9):
         ctx.propagate(it, 1)

@@ -151,6 +151,28 @@ def test_sweep_parity_edge_cases(case):
     _assert_clean(rep, "sweep %s" % case)
 
 
+def test_sweep_level_bound_exact():
+    """Superpixels of 128 x 96 px in 3 views (24 576 px-view pairs, 384 lane
+    passes per level chunk) over 48 levels: the sweep's level bound stops
+    chunks once every level in them is bounded above the second-best cost.
+    Every superpixel must still match the oracle's full sweep, and the bound
+    must have skipped samples."""
+    _say("sweep level bound, large superpixels")
+    w = tiny_custom(256, 192, 2, 2, n_views=3, seed=21, levels=48, labels="grid")
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    ctx.reset_work()
+    ctx.sweep()
+    rep = parity.check_sweep(orc, ctx)
+    _assert_clean(rep, "level-bound sweep")
+    computed, total = ctx.sweep_work()
+    area = orc.sp_stats()[0]
+    _say("sweep samples computed %d of %d" % (computed, total))
+    assert total == int(area.sum()) * 2 * 48
+    assert 0 < computed < total
+    assert ctx.work()[1] == computed
+
+
 def _mixed_size_workload():
     from lfsynth.configs import MethodParams, Workload
     from lfsynth.rig import View, intrinsics, pose_from_centre
