@@ -542,7 +542,10 @@ __host__ __device__ inline int launch_blocks(int nblocks) {
 // stops.  The levels that finish are summed exactly as without the bound, so
 // the outputs are unchanged.  *computed receives the px-view samples
 // computed for levels below k_end.
-constexpr int kBoundCheck = 4;
+#ifndef SLF_BOUND_CHECK
+#define SLF_BOUND_CHECK 4
+#endif
+constexpr int kBoundCheck = SLF_BOUND_CHECK;
 constexpr float kBoundMargin = 1.00001f;
 
 template <int FMT, int KC>
