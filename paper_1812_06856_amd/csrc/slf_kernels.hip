@@ -624,8 +624,9 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
       const float ax = fmaf(A0, pu, fmaf(A1, pv, A2));
       const float ay = fmaf(A3, pu, fmaf(A4, pv, A5));
       const float aw = fmaf(A6, pu, fmaf(A7, pv, A8));
-      // every active lane in an inner view: samples without the bounds test
-      if (__ballot(((inner_views >> iv) & 1ull) == 0ull) == 0ull) {
+      // every active lane in an inner view (neighbours past the 64th are
+      // never taken as inner): samples without the bounds test
+      if (__ballot(iv >= kWave || ((inner_views >> iv) & 1ull) == 0ull) == 0ull) {
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk)
           acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi,

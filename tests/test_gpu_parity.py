@@ -173,6 +173,20 @@ def test_sweep_level_bound_exact():
     assert ctx.work()[1] == computed
 
 
+def test_sweep_parity_many_views():
+    """66 views in a line (65 neighbour views per reference view): more
+    neighbours than lanes in a wave, so per-view tables and flags indexed by
+    lane must not be taken for views past the 64th; then one refinement
+    iteration in lockstep with the oracle."""
+    _say("sweep parity with 65 neighbour views")
+    w = tiny_custom(40, 30, 2, 2, n_views=66, seed=23, levels=12, labels="grid")
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    ctx.sweep()
+    _assert_clean(parity.check_sweep(orc, ctx), "sweep 66 views")
+    _lockstep(w, 1, ctx=ctx, orc=orc)  # refinement: neighbour-view constants in passes of 16
+
+
 def _mixed_size_workload():
     from lfsynth.configs import MethodParams, Workload
     from lfsynth.rig import View, intrinsics, pose_from_centre
