@@ -122,6 +122,7 @@ void free_all(slf_ctx *c) {
   dfree(c->d_pairs);
   dfree(c->d_err);
   dfree(c->d_work);
+  dfree(c->d_claims);
   dfree(c->d_depth_tmp);
 }
 
@@ -478,7 +479,9 @@ int slf_create(int device_ordinal, slf_ctx **out) {
   }
   if (hipMalloc((void **)&c->d_err, sizeof(int)) != hipSuccess ||
       hipMalloc((void **)&c->d_work, kWorkCounters * sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->d_work, 0, kWorkCounters * sizeof(unsigned long long)) != hipSuccess) {
+      hipMemset(c->d_work, 0, kWorkCounters * sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc((void **)&c->d_claims, kPoolQueues * kPoolCounterStride * sizeof(int)) != hipSuccess ||
+      hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device_ordinal) != hipSuccess) {
     free_all(c);
     delete c;
     return SLF_ENOMEM;
@@ -663,7 +666,7 @@ int slf_sweep(slf_ctx *c) {
   if (rc) return rc;
   SweepArgs a;
   sweep_args(c, a);
-  HIP_OR_FAIL(c, launch_sweep(c->p.image_precision, a, c->stream));
+  HIP_OR_FAIL(c, launch_sweep(c->p.image_precision, a, c->d_claims, c->n_cu, c->stream));
   after_sweep(c);
   return SLF_OK;
 }

@@ -74,6 +74,8 @@ struct slf_ctx {
   // device work counters: [0] refinement evals, [1] refinement samples,
   // [2] refinement candidates pruned, [3] sweep samples computed
   unsigned long long *d_work = nullptr;
+  int *d_claims = nullptr;  // claim counters of the persistent sweep launch
+  int n_cu = 0;             // compute units of the device
   float *d_depth_tmp = nullptr;
   int64_t depth_tmp_n = 0;
   int cur = 0;

@@ -133,7 +133,8 @@ hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V
                            const uint8_t *rgb, int S, int *count, int4 *bbox, int *px_off, int *scan_tmp,
                            PixEntry *px, int *area, float2 *centroid, double2 *centroid_d, float4 *colour,
                            int *sp_view, int *err, hipStream_t st);
-hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st);
+// Persistent sweep launch; counters: kPoolQueues x kPoolCounterStride ints of claim counters.
+hipError_t launch_sweep(int fmt, const SweepArgs &a, int *counters, int n_cu, hipStream_t st);
 hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st);
 hipError_t launch_depth(const ViewDev *views_d, const ViewDev &vh, int view, const int *labels,
                         const float4 *tab, float *out, int64_t stride, hipStream_t st);

@@ -498,30 +498,53 @@ __device__ __forceinline__ uint32_t quad_base(const ViewDev &vi) {
   return (uint32_t)vi.quad_off * (uint32_t)kQuadBytes<FMT>;
 }
 
-#ifndef SLF_XCD_REMAP
-#define SLF_XCD_REMAP 1
-#endif
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+static_assert(kPoolQueues == kXcds, "one claim queue per XCD");
 
-// Block index with XCD-aware placement: the hardware hands block b to XCD
-// b mod 8, so logical block (b mod 8) * per + b / 8 gives each XCD one
-// contiguous range of superpixels (in raster order within a view), keeping
-// its gathers inside that XCD's L2.  Returns -1 for padding blocks.
-__device__ __forceinline__ int logical_block(int nblocks) {
-#if SLF_XCD_REMAP
-  const int per = (nblocks + kXcds - 1) / kXcds;
-  const int l = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
-  return l < nblocks ? l : -1;
-#else
-  return (int)blockIdx.x < nblocks ? (int)blockIdx.x : -1;
-#endif
+// Persistent sweep launch over superpixels 0..S-1: they are cut into kXcds
+// contiguous queues (raster order within a view); the waves of workgroup b,
+// which the hardware places on XCD b mod 8, drain queue b mod 8 first, so
+// each XCD's gathers stay inside its own L2, and then steal from the other
+// queues.  One claim is one superpixel, so superpixels of uneven cost (area,
+// chunks stopped early by the level bound) balance across the chip, and
+// every wave exits once all queues are empty.  The same counters serve the
+// pooled kernel below.
+__global__ void k_pool_reset(int *counters) {
+  if (threadIdx.x < kPoolQueues) counters[threadIdx.x * kPoolCounterStride] = 0;
 }
-__host__ __device__ inline int launch_blocks(int nblocks) {
-#if SLF_XCD_REMAP
-  return ((nblocks + kXcds - 1) / kXcds) * kXcds;
-#else
-  return nblocks;
-#endif
+
+// Claims the next index of a queue for the whole wave.  Every lane takes
+// part in the atomic (lane 0 adds one, the others zero) and the wave takes
+// the first lane's old value.  A form with the atomic under `lane == 0`
+// lets the compiler send lanes 1..63 past it on their own (for them it adds
+// nothing), which splits the wave across the claim and, where the caller's
+// body also branches on lane 0, leaves those lanes re-claiming the same
+// index without end.
+__device__ __forceinline__ int claim(int *next) {
+  const int lane = threadIdx.x & (kWave - 1);
+  return __builtin_amdgcn_readfirstlane(atomicAdd(next, lane == 0 ? 1 : 0));
+}
+
+template <class F>
+__device__ __forceinline__ void for_each_claimed(const int S, int *counters, F &&body) {
+  const int home = (int)(blockIdx.x % kPoolQueues);
+  for (int k = 0; k < kPoolQueues; ++k) {
+    const int q = (home + k) % kPoolQueues;
+    const int begin = (int)((int64_t)S * q / kPoolQueues), end = (int)((int64_t)S * (q + 1) / kPoolQueues);
+    int *next = counters + q * kPoolCounterStride;
+    for (;;) {
+      const int g = begin + claim(next);
+      if (g >= end) break;
+      body(g);
+    }
+  }
+}
+
+// Workgroups of a persistent launch: blocks_per_cu resident per CU on every CU.
+static int persistent_blocks(const void *kernel, int n_cu) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  return per_cu * (n_cu > 0 ? n_cu : 1);
 }
 
 // ------------------------------------------------------------------ plane sweep (a2-a5)
@@ -776,22 +799,18 @@ __device__ __forceinline__ void sweep_merge(const SweepArgs &a, const int g, con
 constexpr int kLevelChunk = SLF_LEVEL_CHUNK;
 
 template <int FMT, int KC>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a) {
-  const int blk = logical_block((a.S + kWavesPerBlock - 1) / kWavesPerBlock);
-  if (blk < 0) return;
-  const int g = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + (threadIdx.x >> 6));
-  if (g >= a.S) return;
-  sweep_sp<FMT, KC>(a, g);
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, int *__restrict__ counters) {
+  for_each_claimed(a.S, counters, [&](int g) { sweep_sp<FMT, KC>(a, g); });
 }
 
-hipError_t launch_sweep(int fmt, const SweepArgs &a, hipStream_t st) {
-  const dim3 grid(launch_blocks((a.S + kWavesPerBlock - 1) / kWavesPerBlock)), block(kBlock);
-  switch (fmt) {
-    case SLF_FMT_U8: hipLaunchKernelGGL((k_sweep<SLF_FMT_U8, kLevelChunk>), grid, block, 0, st, a); break;
-    case SLF_FMT_F16: hipLaunchKernelGGL((k_sweep<SLF_FMT_F16, kLevelChunk>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_sweep<SLF_FMT_F32, kLevelChunk>), grid, block, 0, st, a); break;
-  }
-  return hipGetLastError();
+hipError_t launch_sweep(int fmt, const SweepArgs &a, int *counters, int n_cu, hipStream_t st) {
+  const void *k = fmt == SLF_FMT_U8    ? (const void *)k_sweep<SLF_FMT_U8, kLevelChunk>
+                  : fmt == SLF_FMT_F16 ? (const void *)k_sweep<SLF_FMT_F16, kLevelChunk>
+                                       : (const void *)k_sweep<SLF_FMT_F32, kLevelChunk>;
+  hipLaunchKernelGGL(k_pool_reset, dim3(1), dim3(64), 0, st, counters);
+  SweepArgs args = a;
+  void *kargs[] = {(void *)&args, (void *)&counters};
+  return hipLaunchKernel(k, dim3(persistent_blocks(k, n_cu)), dim3(kBlock), kargs, 0, st);
 }
 
 // ------------------------------------------------------------------ refinement (a6-a8)
@@ -1459,19 +1478,29 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Wave
 // Five waves per SIMD (at most 96 VGPRs): the sample loop waits on dependent
 // gathers, and the extra wave hides more of that latency than the few
 // registers it costs (spilled only around candidate generation).
+//
+// One wave per superpixel on a static grid: refinement costs vary much less
+// between superpixels than sweep costs, and the claim loop's state pushes
+// this kernel past 96 VGPRs into spills that cost more than its balancing
+// gains.  The hardware hands workgroup b to XCD b mod 8, so logical block
+// (b mod 8) * per + b / 8 gives each XCD one contiguous range of superpixels
+// (raster order within a view), keeping its gathers inside that XCD's L2.
 template <int FMT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_refine(RefineArgs a) {
   __shared__ WaveLds s_wave[kWavesPerBlock];
+  const int nblocks = (a.S + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int per = (nblocks + kXcds - 1) / kXcds;
+  const int blk = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  if (blk >= nblocks) return;
   const int wid = threadIdx.x >> 6;
-  const int blk = logical_block((a.S + kWavesPerBlock - 1) / kWavesPerBlock);
-  if (blk < 0) return;
   const int g = __builtin_amdgcn_readfirstlane(blk * kWavesPerBlock + wid);
   if (g >= a.S) return;
   refine_sp<FMT>(a, g, s_wave[wid]);
 }
 
 hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st) {
-  const dim3 grid(launch_blocks((a.S + kWavesPerBlock - 1) / kWavesPerBlock)), block(kBlock);
+  const int nblocks = (a.S + kWavesPerBlock - 1) / kWavesPerBlock;
+  const dim3 grid((nblocks + kXcds - 1) / kXcds * kXcds), block(kBlock);
   switch (fmt) {
     case SLF_FMT_U8: hipLaunchKernelGGL((k_refine<SLF_FMT_U8>), grid, block, 0, st, a); break;
     case SLF_FMT_F16: hipLaunchKernelGGL((k_refine<SLF_FMT_F16>), grid, block, 0, st, a); break;
@@ -1486,9 +1515,6 @@ hipError_t launch_refine(int fmt, const RefineArgs &a, hipStream_t st) {
 // its own XCD (workgroup b runs on XCD b mod 8) and then steals from the
 // others in turn, so every wave exits once all queues are empty.  Each item
 // runs the same per-superpixel device functions as the per-rig kernels.
-__global__ void k_pool_reset(int *counters) {
-  if (threadIdx.x < kPoolQueues) counters[threadIdx.x * kPoolCounterStride] = 0;
-}
 
 typedef const __attribute__((address_space(4))) PoolStage ConstStage;
 
@@ -1499,7 +1525,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SL
   // constant address space, as kernel arguments are, so that its fields are
   // loaded into scalar registers.
   ConstStage &st = *(ConstStage *)stage_ptr;
-  const int lane = threadIdx.x & (kWave - 1);
   const int wid = OP == SLF_OP_REFINE ? (int)(threadIdx.x >> 6) : 0;
   const int home = (int)(blockIdx.x % kPoolQueues);
   const int njobs = st.njobs, tile = st.tile;
@@ -1508,9 +1533,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SL
     const int begin = st.qbegin[q], end = st.qend[q];
     int *next = counters + q * kPoolCounterStride;
     for (;;) {
-      int t = 0;
-      if (lane == 0) t = atomicAdd(next, 1);
-      const int item = begin + __builtin_amdgcn_readfirstlane(t);
+      const int item = begin + claim(next);
       if (item >= end) break;
       int lo = 0, hi = njobs - 1;  // the job holding the item
       while (lo < hi) {
