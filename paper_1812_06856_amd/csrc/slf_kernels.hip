@@ -821,6 +821,7 @@ constexpr int kLdsPix = 1024;  // pixels of a superpixel staged in LDS (the rest
 #define SLF_REFINE_CHAINS 2
 #endif
 constexpr int kChains = SLF_REFINE_CHAINS;  // independent gather chains per lane in the energy loop
+static_assert(kLdsPix % (kChains * kWave) == 0, "the staged pixel list pads to whole passes");
 
 typedef __attribute__((address_space(3))) uint32_t LdsU32;
 
@@ -924,6 +925,7 @@ struct SpCtx {
   float invA;                // 1 / |Omega|
   const LdsU32 *pix_lds;     // pixels 0..n_lds-1 as FP16 pairs (u - ub, v - vb), staged in LDS
   int n_lds;                 // staged pixels (0 if an offset exceeds 2048: FP16 holds integers exactly up to there)
+  int n_pad;                 // n_lds rounded up to whole passes; entries n_lds..n_pad-1 hold a NaN pair
   const LdsRing *ring;       // ring neighbours 0..7
   LdsViewConst *vc;          // constants of up to kViewsPerPass neighbour views
   LdsBest *best;             // plane of the running winner
@@ -1082,15 +1084,21 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
             a.lab16 ? buffer_rsrc(a.lab16 + vi.pix_off, 2u * npx) : buffer_rsrc(a.labels + vi.pix_off, 4u * npx);
         const __amdgpu_buffer_rsrc_t tab_rs = buffer_rsrc(a.tabA + 2 * vi.sp_off, 32u * (uint32_t)(vi.gw * vi.gh));
         float sw = 0.f, gx = 0.f;
+        // |X_i| and whether Y_i is non-empty are exact integer results, so
+        // they are kept per wave in scalar registers (a ballot per sample)
+        // rather than per lane and reduced afterwards.
         int nX = 0;
-        bool anyY = false;
+        uint64_t occluded = 0;
         // Branch-free samples in three phases: project the pixel into view
         // i (clamped into the image), gather its label, gather the label's
         // record; the gathers are raw buffer loads bounded by their arrays.
         // Predicates decide what is accumulated.
+        // Predicates are carried as wave masks (a ballot of each compare is
+        // the compare's own result), so they combine in scalar registers and
+        // feed the per-lane selects and the wave-level counts directly.
         struct Proj {
           float iota, w, dx, dy;
-          bool seen;
+          uint64_t seen;  // lanes whose pixel lands inside view i, in front of both cameras
           uint32_t pix;
         };
         // (du, dv): the pixel relative to (ub, vb).  The staged FP16 offsets
@@ -1105,7 +1113,8 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           const float uf = fX0 + floorf(q.dx + 0.5f), vf = fY0 + floorf(q.dy + 0.5f);
           // clamp into the image (a NaN fails the equality and converts to 0)
           const float uc = __builtin_amdgcn_fmed3f(uf, 0.f, Wm1), vc = __builtin_amdgcn_fmed3f(vf, 0.f, Hm1);
-          q.seen = (q.iota > 0.f) & (q.w > 0.f) & (uc == uf) & (vc == vf);
+          q.seen = __builtin_amdgcn_ballot_w64(q.iota > 0.f) & __builtin_amdgcn_ballot_w64(q.w > 0.f) &
+                   __builtin_amdgcn_ballot_w64(uc == uf) & __builtin_amdgcn_ballot_w64(vc == vf);
           q.pix = __umul24((uint32_t)(int)vc, Wv) + (uint32_t)(int)uc;  // sides below 2^16
           return q;
         };
@@ -1119,16 +1128,16 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           const float dr = c.Cs.x - Cl.x, dg = c.Cs.y - Cl.y, db = c.Cs.z - Cl.z;
           const float om = __builtin_amdgcn_exp2f(-fmaf(db, db, fmaf(dg, dg, dr * dr)) * a.inv2alpha2_log2e);
           const float den = fmaf(gt.x, fX0 + q.dx, fmaf(gt.y, fY0 + q.dy, gt.z));  // 1 / D(p^i)
-          const bool front = den > 0.f;
+          const uint64_t back = __builtin_amdgcn_ballot_w64(!(den > 0.f));
           // z <= D(p^i) (1 + tau)  <=>  w den <= (1 + tau) iota   (iota, den > 0)
           const float wd = q.w * den;
-          const bool vis = !front || (wd <= tol * q.iota);
+          const uint64_t vis = q.seen & (back | __builtin_amdgcn_ballot_w64(wd <= tol * q.iota));
           const float dz = (wd - q.iota) * rcp(q.iota * den);  // z - D(p^i)
           const float gk = __builtin_amdgcn_exp2f(-dz * dz * a.inv2sig2_log2e);
-          sw += q.seen ? om : 0.f;
-          nX += (q.seen & vis) ? 1 : 0;
-          gx += (q.seen & vis & front) ? gk : 0.f;
-          anyY |= q.seen & !vis;
+          sw += __builtin_amdgcn_inverse_ballot_w64(q.seen) ? om : 0.f;
+          nX += __popcll(vis);
+          gx += __builtin_amdgcn_inverse_ballot_w64(vis & ~back) ? gk : 0.f;
+          occluded |= q.seen & ~vis;
         };
         auto staged = [&](int p) {
           const __half2 h = __builtin_bit_cast(__half2, (uint32_t)c.pix_lds[p]);
@@ -1138,27 +1147,27 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           const uint32_t uv = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(px_rs, (int)(8u * (uint32_t)p), 0, 0);
           return project((float)((int)(uv & 0xffffu) - c.ub), (float)((int)(uv >> 16) - c.vb));
         };
-        auto one = [&](int p, auto narrow) {
-          const Proj q = listed(p);
+        auto one = [&](int p, bool in, auto narrow) {
+          Proj q = listed(p);
+          q.seen &= __builtin_amdgcn_ballot_w64(in);
           const uint32_t l = label(q, narrow);
           accumulate(q, load_f3(tab_rs, (int)(32u * l)), load_f3(tab_rs, (int)(32u * l + 16u)));
         };
         // kChains pixels per lane per pass keep that many gather chains in
-        // flight; each lane still accumulates its pixels in order.  A chain
-        // past the last staged pixel re-reads the lane's first one and counts
-        // nothing, so every lane makes the same number of passes.
+        // flight; each lane still accumulates its pixels in order.  The
+        // staged list is padded to whole passes with NaN offsets: a NaN pixel
+        // projects to iota = NaN, so it is never seen and adds +0, which
+        // leaves the lane's sums unchanged, and its clamped gathers stay in
+        // bounds.  Every pass is then whole, the trip count is uniform, and
+        // the wave-level counts stay in scalar registers.
         auto samples = [&](auto narrow) {
-          const int n_lds = c.n_lds;
-          for (int p = lane; p < n_lds; p += kChains * kWave) {
+          const int n_pad = c.n_pad;
+          for (int p0 = 0; p0 < n_pad; p0 += kChains * kWave) {
             Proj q[kChains];
             uint32_t l[kChains];
             float3 C[kChains], G[kChains];
 #pragma unroll
-            for (int k = 0; k < kChains; ++k) {
-              const bool in = k == 0 || p + k * kWave < n_lds;
-              q[k] = staged(in ? p + k * kWave : p);
-              q[k].seen &= in;
-            }
+            for (int k = 0; k < kChains; ++k) q[k] = staged(p0 + k * kWave + lane);
 #pragma unroll
             for (int k = 0; k < kChains; ++k) l[k] = label(q[k], narrow);
 #pragma unroll
@@ -1169,7 +1178,10 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
 #pragma unroll
             for (int k = 0; k < kChains; ++k) accumulate(q[k], C[k], G[k]);
           }
-          for (int p = n_lds + lane; p < c.A; p += kWave) one(p, narrow);
+          for (int p0 = c.n_lds; p0 < c.A; p0 += kWave) {
+            const int p = p0 + lane;
+            one(p < c.A ? p : p0, p < c.A, narrow);
+          }
         };
         if (a.lab16)
           samples(std::true_type{});
@@ -1177,8 +1189,8 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           samples(std::false_type{});
         const float swt = wave_sum(sw);
         const float gxt = wave_sum(gx);
-        const int nXt = wave_sum_i(nX);
-        const bool Y = __ballot(anyY) != 0ull;
+        const int nXt = nX;
+        const bool Y = occluded != 0ull;
         const float Si = swt * c.invA;
         const float Vi = nXt > 0 ? Si * gxt * rcp((float)nXt) : 0.f;
         sum += Vi + (Y ? occ : 0.f);
@@ -1305,13 +1317,20 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Wave
   c.ub = (int)floor(cs.x + 0.5);
   c.vb = (int)floor(cs.y + 0.5);
   bool fits = true;
-  for (int p = lane; p < min(c.A, kLdsPix); p += kWave) {
-    const uint32_t uv = a.px[c.poff + p].x;
-    const int du = (int)(uv & 0xffffu) - c.ub, dv = (int)(uv >> 16) - c.vb;
-    fits = fits && abs(du) <= 2048 && abs(dv) <= 2048;
-    pix_lds[p] = __builtin_bit_cast(uint32_t, __floats2half2_rn((float)du, (float)dv));
+  const int n_stage = min(c.A, kLdsPix);
+  const int n_pad = (n_stage + kChains * kWave - 1) / (kChains * kWave) * (kChains * kWave);
+  for (int p = lane; p < n_pad; p += kWave) {
+    uint32_t h = 0x7e007e00u;  // FP16 NaN pair: a pixel that is never seen
+    if (p < n_stage) {
+      const uint32_t uv = a.px[c.poff + p].x;
+      const int du = (int)(uv & 0xffffu) - c.ub, dv = (int)(uv >> 16) - c.vb;
+      fits = fits && abs(du) <= 2048 && abs(dv) <= 2048;
+      h = __builtin_bit_cast(uint32_t, __floats2half2_rn((float)du, (float)dv));
+    }
+    pix_lds[p] = h;
   }
-  c.n_lds = __ballot(!fits) == 0ull ? min(c.A, kLdsPix) : 0;
+  c.n_lds = __ballot(!fits) == 0ull ? n_stage : 0;
+  c.n_pad = c.n_lds > 0 ? n_pad : 0;
   c.pix_lds = (const LdsU32 *)pix_lds;
   wave_lds_sync();
   const int gx = c.s % vw.gw, gy = c.s / vw.gw;
