@@ -1069,9 +1069,13 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
       for (int jv = 0; jv < nv; ++jv) {
         // view base + jv's constants, uniform over the wave
         const ViewConst q = lds_get(c.vc + jv);
-        const float cax = uni_f(q.ax), caxu = uni_f(q.axu), caxv = uni_f(q.axv);
-        const float cay = uni_f(q.ay), cayu = uni_f(q.ayu), cayv = uni_f(q.ayv);
-        const float caw = uni_f(q.aw), cawu = uni_f(q.awu), cawv = uni_f(q.awv);
+        // The multipliers go to scalar registers.  The three addends stay
+        // in vector registers (every lane read the same LDS word): an FMA
+        // can read only one scalar operand, so scalar addends would be
+        // copied back into vector registers on every pass.
+        const float cax = q.ax, caxu = uni_f(q.axu), caxv = uni_f(q.axv);
+        const float cay = q.ay, cayu = uni_f(q.ayu), cayv = uni_f(q.ayv);
+        const float caw = q.aw, cawu = uni_f(q.awu), cawv = uni_f(q.awv);
         const float fX0 = (float)__builtin_amdgcn_readfirstlane(q.X0);
         const float fY0 = (float)__builtin_amdgcn_readfirstlane(q.Y0);
         const ViewDev &vi = ro_at(a.views, ro_at(a.pairs, vw.pair_off + base + jv).i);
