@@ -7,8 +7,8 @@
  * truncated SSD cost (Sec. III-B, eqs. 1-2), the iterative refinement by
  * propagation over a shrinking kernel and triangle normals maximising
  * E = E_c E_s (Sec. III-C, eqs. 3-11, Jacobi ping-pong as in Sec. III-E), and
- * the per-pixel depth readout of the superpixel planes (Sec. III-A: "the
- * output is a set of corresponding depth maps").
+ * the per-pixel depth readout of the superpixel planes (Sec. III-A: the
+ * method's result is one depth map per view).
  *
  * Conventions
  *  - Every call returns an int status: SLF_OK (0) or a negative SLF_E* code.
