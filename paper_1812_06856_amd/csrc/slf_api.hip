@@ -480,11 +480,16 @@ int slf_create(int device_ordinal, slf_ctx **out) {
   if (hipMalloc((void **)&c->d_err, sizeof(int)) != hipSuccess ||
       hipMalloc((void **)&c->d_work, kWorkCounters * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->d_work, 0, kWorkCounters * sizeof(unsigned long long)) != hipSuccess ||
-      hipMalloc((void **)&c->d_claims, kPoolQueues * kPoolCounterStride * sizeof(int)) != hipSuccess ||
-      hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device_ordinal) != hipSuccess) {
+      hipMalloc((void **)&c->d_claims, kPoolQueues * kPoolCounterStride * sizeof(int)) != hipSuccess) {
     free_all(c);
     delete c;
     return SLF_ENOMEM;
+  }
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device_ordinal) != hipSuccess ||
+      c->n_cu < 1) {
+    free_all(c);
+    delete c;
+    return SLF_EDEVICE;
   }
   *out = c;
   return SLF_OK;

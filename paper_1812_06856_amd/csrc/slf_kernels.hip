@@ -8,6 +8,7 @@
 #include <limits.h>
 #include <math.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "slf_internal.h"
@@ -540,11 +541,15 @@ __device__ __forceinline__ void for_each_claimed(const int S, int *counters, F &
   }
 }
 
-// Workgroups of a persistent launch: blocks_per_cu resident per CU on every CU.
-static int persistent_blocks(const void *kernel, int n_cu) {
+// Workgroups of a persistent launch over S items: as many as are resident at
+// once on every CU, but no more than one wave per item (rounded up to whole
+// multiples of kXcds, so each XCD gets its share of workgroups).
+static int persistent_blocks(const void *kernel, int n_cu, int S) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-  return per_cu * (n_cu > 0 ? n_cu : 1);
+  const int resident = per_cu * (n_cu > 0 ? n_cu : 1);
+  const int needed = ((S + kWavesPerBlock - 1) / kWavesPerBlock + kXcds - 1) / kXcds * kXcds;
+  return std::max(1, std::min(resident, needed));
 }
 
 // ------------------------------------------------------------------ plane sweep (a2-a5)
@@ -810,7 +815,7 @@ hipError_t launch_sweep(int fmt, const SweepArgs &a, int *counters, int n_cu, hi
   hipLaunchKernelGGL(k_pool_reset, dim3(1), dim3(64), 0, st, counters);
   SweepArgs args = a;
   void *kargs[] = {(void *)&args, (void *)&counters};
-  return hipLaunchKernel(k, dim3(persistent_blocks(k, n_cu)), dim3(kBlock), kargs, 0, st);
+  return hipLaunchKernel(k, dim3(persistent_blocks(k, n_cu, a.S)), dim3(kBlock), kargs, 0, st);
 }
 
 // ------------------------------------------------------------------ refinement (a6-a8)
