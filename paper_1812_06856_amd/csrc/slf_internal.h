@@ -61,6 +61,7 @@ struct SweepArgs {
   uint64_t seed;
   int jitter;
   float T255;          // truncation in squared 0..255 units
+  int exact_margin;    // 1: levels stop against the second-best complete cost (exact margin), 0: the best
   const float4 *colour;  // mean colour per superpixel
   float4 *planes;      // out
   float4 *tab;         // out: per superpixel {colour, inverse-depth row (g0, g1, g2, 0)}

@@ -561,15 +561,19 @@ static int persistent_blocks(const void *kernel, int n_cu, int S) {
 // ties.
 // Costs of levels [k_begin, k_end) of superpixel g: the smallest (ties: the
 // lowest level) and the second smallest, uniform over the wave.
-// Every kBoundCheck pixel passes, once two levels are complete, the chunk's
-// partial costs are compared with the second-best complete cost.  Each
-// sample costs >= 0, so a partial cost bounds the level's cost from below;
-// when every level of the chunk is bounded above the second best (times
-// kBoundMargin, far above the rounding of the differently ordered partial
-// sums) none of them can be the best or the second best, and the chunk
+// Every kBoundCheck pixel passes the chunk's partial costs are compared with
+// a complete level's cost: the second best when a.exact_margin is set (once
+// two levels are complete), else the best.  Each sample costs >= 0, so a
+// partial cost bounds the level's cost from below (per lane the sums only
+// grow, and FP addition is monotone, so this holds for the rounded sums as
+// well); when every level of the chunk is bounded above the reference
+// (times kBoundMargin, a further margin) none of them can be the best, nor
+// tie with it, nor (with exact_margin) be the second best, and the chunk
 // stops.  The levels that finish are summed exactly as without the bound, so
-// the outputs are unchanged.  *computed receives the px-view samples
-// computed for levels below k_end.
+// the level, plane and cost are unchanged; without exact_margin the second
+// best is taken over the levels that finished, an upper bound of the exact
+// one.  *computed receives the px-view samples computed for levels below
+// k_end.
 #ifndef SLF_BOUND_CHECK
 #define SLF_BOUND_CHECK 4
 #endif
@@ -630,6 +634,7 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
     uint32_t qbase = 0;
     const int n_pass = (P + kWave - 1) / kWave;
     int passes = n_pass;
+    const float bound_ref = a.exact_margin ? second : best;  // complete levels change only between chunks
     for (int it = 0; it < n_pass; ++it) {
       if (lane + it * kWave < P) {
       if (iv != cur) {
@@ -671,8 +676,8 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
         ++iv;
       }
       }
-      if ((it & (kBoundCheck - 1)) == kBoundCheck - 1 && it + 1 < n_pass && second < INFINITY) {
-        const float lim = second * kBoundMargin;
+      if ((it & (kBoundCheck - 1)) == kBoundCheck - 1 && it + 1 < n_pass && bound_ref < INFINITY) {
+        const float lim = bound_ref * kBoundMargin;
         bool bounded = true;
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk)

@@ -154,23 +154,43 @@ def test_sweep_parity_edge_cases(case):
 def test_sweep_level_bound_exact():
     """Superpixels of 128 x 96 px in 3 views (24 576 px-view pairs, 384 lane
     passes per level chunk) over 48 levels: the sweep's level bound stops
-    chunks once every level in them is bounded above the second-best cost.
-    Every superpixel must still match the oracle's full sweep, and the bound
-    must have skipped samples."""
+    chunks once every level in them is bounded above a complete level's cost.
+    With exact_sweep_margin that is the second best, and the margin must match
+    the oracle's; by default it is the best, which must leave the level, plane
+    and cost bit for bit as they are and give a margin no smaller than the
+    exact one, with fewer samples computed.  Both must match the oracle's full
+    sweep, and both must have skipped samples."""
     _say("sweep level bound, large superpixels")
     w = tiny_custom(256, 192, 2, 2, n_views=3, seed=21, levels=48, labels="grid")
-    ctx = _ctx(w)
     orc = _oracle(w)
-    ctx.reset_work()
-    ctx.sweep()
-    rep = parity.check_sweep(orc, ctx)
-    _assert_clean(rep, "level-bound sweep")
-    computed, total = ctx.sweep_work()
     area = orc.sp_stats()[0]
-    _say("sweep samples computed %d of %d" % (computed, total))
-    assert total == int(area.sum()) * 2 * 48
-    assert 0 < computed < total
-    assert ctx.work()[1] == computed
+    runs = {}
+    for exact in (1, 0):
+        ctx = _ctx(w, exact_sweep_margin=exact)
+        ctx.reset_work()
+        ctx.sweep()
+        _assert_clean(parity.check_sweep(orc, ctx), "level-bound sweep, exact margin %d" % exact)
+        computed, total = ctx.sweep_work()
+        _say("exact margin %d: sweep samples computed %d of %d" % (exact, computed, total))
+        assert total == int(area.sum()) * 2 * 48
+        assert 0 < computed < total
+        assert ctx.work()[1] == computed
+        runs[exact] = (parity.gpu_state(ctx, orc.V), computed)
+        ctx.close()
+    (P1, C1, K1, M1), n1 = runs[1]
+    (P0, C0, K0, M0), n0 = runs[0]
+    assert np.array_equal(P1, P0) and np.array_equal(C1, C0) and np.array_equal(K1, K0)
+    full = K1 >= 0
+    assert (M0[full] >= M1[full]).all()
+    assert n0 <= n1
+    for v in range(orc.V):
+        for s in range(int(orc.sp_off[v + 1] - orc.sp_off[v])):
+            g = int(orc.sp_off[v]) + s
+            if area[g] == 0:
+                continue
+            _, _, k_o, m_o = orc.sweep_sp(v, s)
+            if int(K1[g]) == k_o:
+                assert abs(float(M1[g]) - m_o) <= parity.MARGIN + parity.REL * abs(m_o), (v, s, M1[g], m_o)
 
 
 def test_sweep_parity_many_views():
@@ -429,5 +449,8 @@ def test_error_paths():
     with pytest.raises(slf.SlfError) as e:
         ctx.set_params(slf.default_params(d_min=3.0, d_max=2.0))
     assert e.value.status == slf.SLF_EINVAL
+    with pytest.raises(slf.SlfError) as e:
+        ctx.set_params(slf.default_params(exact_sweep_margin=2))
+    assert e.value.status == slf.SLF_EINVAL and "exact_sweep_margin" in ctx.last_error()
     ctx.propagate(1, 1)
     ctx.synchronize()
