@@ -114,6 +114,12 @@ __device__ __forceinline__ float ring_sum(float x) {
   return rd_f(x, 0);
 }
 
+// Makes earlier LDS writes of any lane of this wave visible to its later reads.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Lane `l`'s value, uniform over the wave (l must be wave-uniform).
@@ -580,6 +586,78 @@ static int persistent_blocks(const void *kernel, int n_cu, int S) {
 constexpr int kBoundCheck = SLF_BOUND_CHECK;
 constexpr float kBoundMargin = 1.00001f;
 
+// Chunk order.  Bounded against the best complete cost, a chunk stops early
+// once a good level is known, so a coarse pre-pass first scores one level per
+// chunk (its middle one) on every kCoarseStride-th pixel pass, and the chunks
+// then run in increasing coarse cost (one byte per chunk in the wave's LDS).
+// The order changes only which samples the bound skips: the tie rule below
+// (a lower cost, or an equal one at a lower level) gives the level a pass in
+// level order gives.  Returns false (level order) for fewer than 3 or more
+// than 64 chunks, or fewer than 2 kCoarseStride pixel passes.  The pre-pass
+// samples are added to *computed.
+#ifndef SLF_COARSE_STRIDE
+#define SLF_COARSE_STRIDE 8
+#endif
+constexpr int kCoarseStride = SLF_COARSE_STRIDE;  // 0: chunks in level order
+
+template <int FMT, int KC>
+__device__ __forceinline__ bool coarse_order(const SweepArgs &a, const int g, const int v, const int s,
+                                             const ViewDev &vw, const int A, const int k_begin, const int k_end,
+                                             uint8_t *order, uint64_t &computed) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int P = A * vw.n_pairs;
+  const int n_pass = (P + kWave - 1) / kWave;
+  const int n_chunks = (k_end - k_begin + KC - 1) / KC;
+  if (kCoarseStride <= 0 || n_chunks < 3 || n_chunks > kWave || n_pass < 2 * kCoarseStride) return false;
+  const int poff = a.px_off[g];
+  const __amdgpu_buffer_rsrc_t qrs = buffer_rsrc(a.quads, a.quad_bytes);
+  float mine = 0.f;  // lane c: coarse cost of chunk c
+  for (int c0 = 0; c0 < n_chunks; c0 += KC) {
+    float q[KC], acc[KC];
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int cb = k_begin + min(c0 + kk, n_chunks - 1) * KC;
+      q[kk] = (float)level_q(a.seed, a.jitter, a.qmin, a.dq, v, s, cb + min(KC / 2, k_end - cb - 1));
+      acc[kk] = 0.f;
+    }
+    for (int it = 0; it < n_pass; it += kCoarseStride) {
+      const int j = lane + it * kWave;
+      if (j < P) {
+        const int iv = j / A, p = j - iv * A;
+        const PairDev &pg = a.pairs[vw.pair_off + iv];
+        const ViewDev &vi = a.views[pg.i];
+        const PixEntry e = a.px[poff + p];
+        const float pu = (float)(e.x & 0xffffu), pv = (float)(e.x >> 16);
+        const float r0 = (float)(e.y & 255u), g0 = (float)((e.y >> 8) & 255u), b0 = (float)((e.y >> 16) & 255u);
+        const float ax = fmaf(pg.A[0], pu, fmaf(pg.A[1], pv, pg.A[2]));
+        const float ay = fmaf(pg.A[3], pu, fmaf(pg.A[4], pv, pg.A[5]));
+        const float aw = fmaf(pg.A[6], pu, fmaf(pg.A[7], pv, pg.A[8]));
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk)
+          acc[kk] += tssd_sample<FMT>(fmaf(q[kk], pg.b[0], ax), fmaf(q[kk], pg.b[1], ay), fmaf(q[kk], pg.b[2], aw),
+                                      (float)(vi.W - 1), (float)(vi.H - 1), vi.W, vi.H, qrs, quad_base<FMT>(vi), r0,
+                                      g0, b0, a.T255);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const float sum = wave_sum(acc[kk]);
+      if (lane == c0 + kk) mine = sum;
+    }
+    const int used = (n_pass + kCoarseStride - 1) / kCoarseStride, last = (used - 1) * kCoarseStride;
+    computed += (uint64_t)((used - 1) * kWave + min(kWave, P - last * kWave)) * (uint64_t)min(KC, n_chunks - c0);
+  }
+  // rank of chunk `lane` in increasing coarse cost (ties: lower chunk first)
+  int rank = 0;
+  for (int c = 0; c < n_chunks; ++c) {
+    const float other = __shfl(mine, c, kWave);
+    rank += (other < mine || (other == mine && c < lane)) ? 1 : 0;
+  }
+  if (lane < n_chunks) order[rank] = (uint8_t)lane;
+  wave_lds_sync();
+  return true;
+}
+
 template <int FMT, int KC>
 __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, const int v, const int s,
                                              const ViewDev &vw, const int A, const int k_begin, const int k_end,
@@ -589,7 +667,12 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
   const int P = A * N;
   const int poff = a.px_off[g];
   const int4 bb = ro_at(a.bbox, g);  // pixel bounding box (x0, y0, x1, y1)
-  for (int k0 = k_begin; k0 < k_end; k0 += KC) {
+  __shared__ uint8_t s_order[kWavesPerBlock][kWave];  // chunk order of each wave of the workgroup
+  uint8_t *order = s_order[threadIdx.x >> 6];
+  const bool ordered = coarse_order<FMT, KC>(a, g, v, s, vw, A, k_begin, k_end, order, computed);
+  const int n_chunks = (k_end - k_begin + KC - 1) / KC;
+  for (int ci = 0; ci < n_chunks; ++ci) {
+    const int k0 = k_begin + KC * (ordered ? __builtin_amdgcn_readfirstlane((int)order[ci]) : ci);
     float q[KC];
 #pragma unroll
     for (int j = 0; j < KC; ++j) q[j] = (float)level_q(a.seed, a.jitter, a.qmin, a.dq, v, s, k0 + j);
@@ -689,12 +772,12 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
       }
     }
     computed += (uint64_t)min(P, passes * kWave) * (uint64_t)min(KC, k_end - k0);
-    if (passes < n_pass) continue;  // no level of this chunk can be best or second best
+    if (passes < n_pass) continue;  // no level of this chunk can be the best (or, with exact_margin, the second best)
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       const float C = wave_sum(acc[kk]);
       if (k0 + kk < k_end) {
-        if (C < best) {
+        if (C < best || (C == best && k0 + kk < kbest)) {
           second = best;
           best = C;
           kbest = k0 + kk;
@@ -834,12 +917,6 @@ constexpr int kChains = SLF_REFINE_CHAINS;  // independent gather chains per lan
 static_assert(kLdsPix % (kChains * kWave) == 0, "the staged pixel list pads to whole passes");
 
 typedef __attribute__((address_space(3))) uint32_t LdsU32;
-
-// Makes earlier LDS writes of any lane of this wave visible to its later reads.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 __device__ __forceinline__ float3 load_f3(__amdgpu_buffer_rsrc_t rs, int off) {
   typedef float f3v __attribute__((ext_vector_type(3)));
