@@ -581,7 +581,7 @@ static int persistent_blocks(const void *kernel, int n_cu, int S) {
 // one.  *computed receives the px-view samples computed for levels below
 // k_end.
 #ifndef SLF_BOUND_CHECK
-#define SLF_BOUND_CHECK 4
+#define SLF_BOUND_CHECK 2
 #endif
 constexpr int kBoundCheck = SLF_BOUND_CHECK;
 constexpr float kBoundMargin = 1.00001f;
