@@ -73,13 +73,15 @@ typedef struct {
     int32_t homography_fp64;    /* must be 1: refinement composes each candidate's homographies in FP64 on
                                    the device, re-centred on the superpixel (per-sample work is FP32) */
     int32_t energy_mode;        /* 0: E = E_c E_s (eq. 3); 1: E = -normalised TSSD (data-only test mode) */
-    int32_t exact_sweep_margin; /* the sweep stops a level once its partial cost (a sum of terms >= 0)
-                                   exceeds a complete level's cost.  0 (default): the best complete
-                                   cost, so the chosen level, plane and cost are exact and the sweep
-                                   margin is an upper bound of the exact one (the second best is taken
-                                   over the levels evaluated in full); 1: the second-best complete
-                                   cost, so the margin is exact too, at more work.  The refinement
-                                   does not read the sweep margin. */
+    int32_t exact_margin;       /* work skipped by exact bounds.  The sweep stops a level once its
+                                   partial cost (a sum of terms >= 0) exceeds a complete level's cost;
+                                   the refinement stops a candidate once its energy bound falls below
+                                   an evaluated candidate's energy.  0 (default): against the best so
+                                   far, so the chosen level or candidate, plane and cost or energy are
+                                   exact, and the margin (second best against best) is an upper bound
+                                   of the exact one, the second best being taken over what was
+                                   evaluated in full; 1: against the second best, so the margins are
+                                   exact too, at more work.  No stage reads a margin. */
 } slf_params;
 
 enum { SLF_IMAGE_U8 = 0, SLF_IMAGE_F16 = 1, SLF_IMAGE_F32 = 2 };
@@ -87,7 +89,7 @@ enum { SLF_IMAGE_U8 = 0, SLF_IMAGE_F16 = 1, SLF_IMAGE_F32 = 2 };
 /* Fills p with the defaults: levels 64, [2, 8], seed 0x5EED, jitter on,
  * T = 0.04, sigma = 0.05, alpha = 0.1, eta = 0.5, tau = 1e-3, step 5, radius
  * derived, all terms, U8 images, FP64 homography composition, paper energy,
- * sweep margin as an upper bound (exact_sweep_margin 0). */
+ * margins as upper bounds (exact_margin 0). */
 void slf_default_params(slf_params *p);
 
 typedef struct slf_ctx slf_ctx;

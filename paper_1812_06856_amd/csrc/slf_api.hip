@@ -76,7 +76,7 @@ int params_check(slf_ctx *c, const slf_params *p) {
   if (p->term_mask > 7u) return c->fail(SLF_EINVAL, "term_mask must be in [0, 7]");
   if (p->image_precision < 0 || p->image_precision > 2) return c->fail(SLF_EINVAL, "bad image_precision");
   if (p->energy_mode < 0 || p->energy_mode > 1) return c->fail(SLF_EINVAL, "bad energy_mode");
-  if (p->exact_sweep_margin < 0 || p->exact_sweep_margin > 1) return c->fail(SLF_EINVAL, "bad exact_sweep_margin");
+  if (p->exact_margin < 0 || p->exact_margin > 1) return c->fail(SLF_EINVAL, "bad exact_margin");
   if (p->homography_fp64 != 1) return c->fail(SLF_EUNSUPPORTED, "homography_fp64 must be 1");
   return SLF_OK;
 }
@@ -357,7 +357,7 @@ void slf::sweep_args(const slf_ctx *c, SweepArgs &a) {
   a.seed = c->p.seed;
   a.jitter = c->p.jitter;
   a.T255 = c->p.tssd_T * 255.f * 255.f;
-  a.exact_margin = c->p.exact_sweep_margin;
+  a.exact_margin = c->p.exact_margin;
   a.planes = c->d_planes[c->cur];
   a.colour = c->d_colour;
   a.tab = c->d_tab[c->cur];
@@ -403,6 +403,7 @@ void slf::refine_args(const slf_ctx *c, int iter, RefineArgs &a) {
   a.S = c->S;
   a.kernel_step = c->p.kernel_step;
   a.energy_mode = c->p.energy_mode;
+  a.exact_margin = c->p.exact_margin;
   a.term_mask = c->p.term_mask;
   a.inv2sig2 = 1.f / (2.f * c->p.sigma * c->p.sigma);
   a.inv2alpha2 = 1.f / (2.f * c->p.alpha * c->p.alpha);
@@ -449,7 +450,7 @@ void slf_default_params(slf_params *p) {
   p->image_precision = SLF_IMAGE_U8;
   p->homography_fp64 = 1;
   p->energy_mode = 0;
-  p->exact_sweep_margin = 0;
+  p->exact_margin = 0;
 }
 
 const char *slf_status_string(int s) {

@@ -96,6 +96,7 @@ struct RefineArgs {
   int iter;
   int kernel_step;
   int energy_mode;
+  int exact_margin;  // 1: candidates stop against the second-best energy (exact margin), 0: the best
   unsigned term_mask;
   float inv2sig2, inv2alpha2, eta, occ_tol, T255;
   float inv2sig2_log2e, inv2alpha2_log2e;  // the same scales times log2(e), for exp2

@@ -1034,13 +1034,14 @@ __device__ __forceinline__ double bcast_d(double x, int l) {
 }
 
 // Energy E = E_c E_s (eqs. 3-11) of the 3D plane n . X = delta in camera r.
-// `e_floor` is the second-best energy so far.  Each view's term of E_c is at
-// most 1 + occ (every S_i, V_i and Gaussian mean is at most 1), so after j of
-// the N views E_c <= (their sum + (N - j)(1 + occ)) / N.  Once E_s times that
-// bound lies below e_floor, with a margin far above FP32 rounding, the
-// candidate can change neither the winner nor the margin: *pruned is set and
-// the remaining views are skipped (results are unchanged).  *views receives
-// the number of neighbour views sampled.
+// `e_floor` is an energy already reached (the best or the second best so
+// far).  Each view's term of E_c is at most 1 + occ (every S_i, V_i and
+// Gaussian mean is at most 1), so after j of the N views E_c <= (their sum +
+// (N - j)(1 + occ)) / N.  Once E_s times that bound lies below e_floor, with a
+// margin far above FP32 rounding, the candidate cannot reach e_floor: it can
+// change neither the winner nor (with the second best as floor) the margin.
+// *pruned is set and the remaining views are skipped.  *views receives the
+// number of neighbour views sampled.
 template <int FMT>
 __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, double nx, double ny, double nz,
                         double delta, float e_floor, bool &pruned, int &views) {
@@ -1342,7 +1343,11 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
     cd.slot = __builtin_amdgcn_readfirstlane(cd.slot);
     bool pruned;
     int views;
-    const float E = uni_f(energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta, b.second, pruned, views));
+    // A candidate whose energy bound falls below the floor cannot replace the
+    // best (a strictly larger energy does), nor tie with it; with exact_margin
+    // the floor is the second best, so it cannot be the second best either.
+    const float floor_E = a.exact_margin ? b.second : (b.slot >= 0 ? b.E : -INFINITY);
+    const float E = uni_f(energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta, floor_E, pruned, views));
     ++b.evaluated;
     b.view_samples += views;
     if (pruned) {  // bounded below the second best: no change

@@ -39,7 +39,7 @@ class slf_params(ctypes.Structure):
                 ("eta", ctypes.c_float), ("occ_tol", ctypes.c_float), ("kernel_step", ctypes.c_int32),
                 ("kernel_radius_init", ctypes.c_int32), ("term_mask", ctypes.c_uint32),
                 ("image_precision", ctypes.c_int32), ("homography_fp64", ctypes.c_int32),
-                ("energy_mode", ctypes.c_int32), ("exact_sweep_margin", ctypes.c_int32)]
+                ("energy_mode", ctypes.c_int32), ("exact_margin", ctypes.c_int32)]
 
 
 class slf_pool_config(ctypes.Structure):

@@ -155,7 +155,7 @@ def test_sweep_level_bound_exact():
     """Superpixels of 128 x 96 px in 3 views (24 576 px-view pairs, 384 lane
     passes per level chunk) over 48 levels: the sweep's level bound stops
     chunks once every level in them is bounded above a complete level's cost.
-    With exact_sweep_margin that is the second best, and the margin must match
+    With exact_margin that is the second best, and the margin must match
     the oracle's; by default it is the best, which must leave the level, plane
     and cost bit for bit as they are and give a margin no smaller than the
     exact one, with fewer samples computed.  Both must match the oracle's full
@@ -166,7 +166,7 @@ def test_sweep_level_bound_exact():
     area = orc.sp_stats()[0]
     runs = {}
     for exact in (1, 0):
-        ctx = _ctx(w, exact_sweep_margin=exact)
+        ctx = _ctx(w, exact_margin=exact)
         ctx.reset_work()
         ctx.sweep()
         _assert_clean(parity.check_sweep(orc, ctx), "level-bound sweep, exact margin %d" % exact)
@@ -283,6 +283,34 @@ def test_refine_lockstep_random_state():
     ctx.propagate(1, 1)
     rep = parity.check_refine(orc, ctx, A64, 1)
     _assert_clean(rep, "random-state refine")
+
+
+def test_refine_pruning_floor_modes():
+    """Refinement candidates stop once their energy bound falls below the best
+    energy so far (default) or the second best (exact_margin = 1).  Both must
+    give the same winners, planes and energies bit for bit, the default's
+    margins no smaller than the exact ones, more candidates pruned and fewer
+    samples.  The exact mode is also checked in lockstep against the oracle."""
+    _say("refinement pruning against the best vs the second best")
+    w = config1()
+    res = {}
+    for exact in (1, 0):
+        ctx = _ctx(w, exact_margin=exact)
+        ctx.sweep()
+        ctx.reset_work()
+        ctx.propagate(1, 2)
+        res[exact] = (parity.gpu_state(ctx, len(w.rig.views)), ctx.work_detail())
+        ctx.close()
+    (P1, E1, K1, M1), (ev1, smp1, pr1) = res[1]
+    (P0, E0, K0, M0), (ev0, smp0, pr0) = res[0]
+    _say("exact: %d evaluated, %d samples, %d pruned; default: %d, %d, %d" % (ev1, smp1, pr1, ev0, smp0, pr0))
+    assert np.array_equal(P1, P0) and np.array_equal(E1, E0) and np.array_equal(K1, K0)
+    full = K1 >= 0
+    assert (M0[full] >= M1[full]).all()
+    assert ev0 == ev1 and pr0 >= pr1 and smp0 <= smp1
+    ctx = _ctx(w, exact_margin=1)
+    _lockstep(w, 1, ctx=ctx)
+    ctx.close()
 
 
 def test_refine_lockstep_far_pixels():
@@ -450,7 +478,7 @@ def test_error_paths():
         ctx.set_params(slf.default_params(d_min=3.0, d_max=2.0))
     assert e.value.status == slf.SLF_EINVAL
     with pytest.raises(slf.SlfError) as e:
-        ctx.set_params(slf.default_params(exact_sweep_margin=2))
-    assert e.value.status == slf.SLF_EINVAL and "exact_sweep_margin" in ctx.last_error()
+        ctx.set_params(slf.default_params(exact_margin=2))
+    assert e.value.status == slf.SLF_EINVAL and "exact_margin" in ctx.last_error()
     ctx.propagate(1, 1)
     ctx.synchronize()
