@@ -40,6 +40,8 @@ def test_params_struct_layout_matches_header():
     p = slf.default_params()
     assert p.struct_size == ctypes.sizeof(slf.slf_params)
     assert p.levels == 64 and abs(p.tssd_T - 0.04) < 1e-7 and p.kernel_step == 5 and p.term_mask == 7
+    # the last field: a layout mismatch shows here first
+    assert p.energy_mode == 0 and p.exact_margin == 0 and p.homography_fp64 == 1
 
 
 def test_status_strings():
