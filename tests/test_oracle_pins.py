@@ -79,7 +79,7 @@ def test_levels_lie_in_their_bins_and_jitter_off_is_exact():
 # ----------------------------------------------------------------- homography
 
 def test_p1_identity_cameras_give_identity_homography_and_zero_cost():
-    """North-star fact: identical cameras give H = I for every plane, so every
+    """Pinned fact: identical cameras give H = I for every plane, so every
     sweep level costs 0, all tie, and the first level wins (ties -> smallest k)."""
     r = _ident_rig()
     orc = Oracle(r, params(levels=16, d_min=2.0, d_max=8.0))
@@ -200,7 +200,7 @@ def _integer_disparity_workload():
 
 
 def test_p4_integer_disparity_sweep_recovers_true_level_exactly():
-    """North-star fact: a noise-free rendered planar scene gives the true plane.
+    """Pinned fact: a noise-free rendered planar scene gives the true plane.
     Fronto-parallel planes at integer disparities, levels one disparity apart,
     no jitter: every pure superpixel (one scene plane, seen unoccluded and at
     least 1 px inside every neighbour view) has zero cost at its true level and
@@ -339,7 +339,7 @@ def test_smoothness_extrapolation_uses_the_plane_not_its_centroid_depth():
 # ----------------------------------------------------------------- consistency (eqs. 8-11)
 
 def test_p8a_consistent_identity_views_give_unit_consistency():
-    """North-star fact: identical cameras, equal labels, colours and planes in
+    """Pinned fact: identical cameras, equal labels, colours and planes in
     all views: S_i = 1, every pixel in X with zero depth difference, Y empty,
     so every view contributes 1 and E_c = 1 (eqs. 8-10)."""
     r = _ident_rig(16, 12, 4, 3, seed=5, n=3)
@@ -622,7 +622,7 @@ def test_p12_refinement_is_a_strict_argmax_over_its_candidates():
 
 
 def test_p13_data_only_mode_never_worsens_and_equals_brute_force_on_reachable_grid():
-    """North-star fact: propagation never ends worse than exhaustive search over
+    """Pinned fact: propagation never ends worse than exhaustive search over
     the same hypothesis set.  Data-only energy (E = -normalised TSSD): the cost
     never increases across iterations, and on a 3x3 grid whose kernel reaches
     every cell in iteration 1 the propagation winner equals brute force over
