@@ -28,8 +28,8 @@
  *    is cell (k mod grid_w, k div grid_w); cells may be empty.
  *  - A plane is stored per superpixel as 4 floats (d, nx, ny, nz): the unit
  *    normal n in the view's camera frame and the depth d of the plane at the
- *    superpixel's centroid (Sec. II: planes are "a single depth value at a
- *    superpixel centroid and a normal vector").  Empty cells hold zeros.
+ *    superpixel's centroid (Sec. III-A: each superpixel's plane is given by
+ *    its depth and orientation at the centroid).  Empty cells hold zeros.
  */
 #ifndef SLF_H
 #define SLF_H
@@ -118,8 +118,10 @@ int slf_set_neighbors(slf_ctx *ctx, int view, int n, const int32_t *views);
 /* RGB8 image of a view, H rows of W * 3 bytes separated by row_stride_bytes
  * (>= 3 W).  is_device = 1: rgb is a device pointer read on the stream. */
 int slf_set_image_rgb8(slf_ctx *ctx, int view, const uint8_t *rgb, int64_t row_stride_bytes, int is_device);
-/* Superpixel labels of a view, int32, H rows separated by row_stride_elems
- * (>= W); grid_w * grid_h <= 2^24 cells.  Host labels are range-checked here
+/* Superpixel labels of a view (Sec. III-A: the SLIC segmentation, read as
+ * an approximately regular grid of cells with a conventional neighbour
+ * system), int32, H rows separated by row_stride_elems (>= W); grid_w *
+ * grid_h <= 2^24 cells.  Host labels are range-checked here
  * (SLF_EINVAL); device labels are checked when superpixels are built and an
  * out-of-range label makes slf_sweep / slf_propagate fail with SLF_EINVAL. */
 int slf_set_labels(slf_ctx *ctx, int view, const int32_t *labels, int64_t row_stride_elems, int grid_w,
@@ -144,7 +146,8 @@ int slf_prepare(slf_ctx *ctx);
  * SLF_ESTATE unless cameras, images and labels are set for every view. */
 int slf_sweep(slf_ctx *ctx);
 /* Replaces the current planes of a view ([grid_w * grid_h][4] host floats,
- * see the plane convention).  Non-empty cells need a finite d > 0 and a unit
+ * see the plane convention; Sec. III-E: the state the next refinement
+ * iteration reads, as the initial planes of Sec. III-B are).  Non-empty cells need a finite d > 0 and a unit
  * normal (within 1e-3) facing the camera at the cell's centroid; SLF_EINVAL
  * otherwise.  Entries of empty cells are ignored.  Needs cameras, images and
  * labels (SLF_ESTATE). */
@@ -166,8 +169,10 @@ int slf_propagate(slf_ctx *ctx, int first_iter, int n_iters);
  * cost after slf_sweep and the energy after slf_propagate; choice the level or
  * slot (-1 for empty cells); margin as described above.  Synchronises. */
 int slf_get_planes(slf_ctx *ctx, int view, float *planes, float *energy_or_cost, int32_t *choice, float *margin);
-/* Per-pixel depth D(p) of the view from its superpixel's plane (0 where the
- * plane does not face the camera): H rows separated by row_stride_elems.
+/* Per-pixel depth D(p) of the view from its superpixel's plane (Sec. III-A:
+ * the depth values of each superpixel are described by its plane; the
+ * method outputs one depth map per view), 0 where the plane does not face
+ * the camera: H rows separated by row_stride_elems.
  * is_device = 0 synchronises and copies to the host; 1 writes the device
  * buffer asynchronously. */
 int slf_get_depth(slf_ctx *ctx, int view, float *out, int64_t row_stride_elems, int is_device);
@@ -179,22 +184,27 @@ int slf_get_superpixels(slf_ctx *ctx, int view, int32_t *area, float *centroid, 
  * hypotheses decided (one (view, superpixel, plane) score: a sweep level or
  * a refinement candidate).  samples: px-view samples computed (one pixel
  * tested in one neighbour view under one plane).  pruned: refinement
- * candidates decided before their consistency term was complete: after
- * each neighbour view, the smoothness times an upper bound of the
+ * candidates decided before their consistency term (eq. 8) was complete:
+ * after each neighbour view, the smoothness times an upper bound of the
  * consistency term (views left contributing at most 1 + occlusion weight)
- * lay below the second-best energy so far, so they could change neither
- * the winner nor the margin.  They count in evals; only the samples of the
- * views computed count in samples.  Sweep levels are decided the same way
- * (see slf_get_sweep_work): every level counts in evals, only the samples
+ * lay below the floor, so the candidate could not change the result.  The
+ * floor is the best energy so far by default (exact_margin = 0: winner,
+ * plane and energy are exact and the margin is an upper bound of the exact
+ * one) or the second best (exact_margin = 1: the margin is exact too).
+ * Pruned candidates count in evals; only the samples of the views computed
+ * count in samples.  Sweep levels are decided the same way (see
+ * slf_get_sweep_work): every level counts in evals, only the samples
  * computed count in samples.  Synchronises. */
 int slf_get_work(slf_ctx *ctx, uint64_t *evals, uint64_t *samples, uint64_t *pruned);
 /* Sweep work since the last reset; either output may be NULL.  The sweep
  * (Sec. III-B, eq. 2) scores levels in chunks; each px-view sample costs
  * >= 0, so a level's partial cost bounds its cost from below, and a chunk
- * stops once every level in it is bounded above the second-best complete
- * cost: none of them can be the chosen level or the second best, so plane,
- * cost, level and margin are those of the full sweep.  computed: px-view
- * samples the sweeps computed; total: the samples of a sweep without that
+ * stops once every level in it is bounded above a complete level's cost:
+ * the best so far by default (exact_margin = 0: level, plane and cost are
+ * those of the full sweep and the margin is an upper bound of the exact
+ * one), the second best with exact_margin = 1 (the margin is exact too).
+ * computed: px-view samples the sweeps computed (the coarse pre-pass that
+ * orders the chunks included); total: the samples of a sweep without that
  * bound (pixels x neighbour views x levels).  Synchronises. */
 int slf_get_sweep_work(slf_ctx *ctx, uint64_t *computed, uint64_t *total);
 int slf_reset_work(slf_ctx *ctx);

@@ -853,7 +853,8 @@ __device__ __forceinline__ void sweep_part(const SweepArgs &a, const int g, cons
   const int kb = part * per, ke = min(a.levels, kb + per);
   float best = INFINITY, second = INFINITY;
   int kbest = 0;
-  uint64_t computed = 0;  // the bound uses this part's own second best, so its two smallest stay exact
+  uint64_t computed = 0;  // the bound references this part's own complete levels (best, or second best
+                          // with exact_margin), so the part's best stays exact and the merge is too
   if (kb < ke) sweep_levels<FMT, KC>(a, g, v, s, vw, A, kb, ke, best, second, kbest, computed);
   if (lane == 0) {
     parts[part] = make_float4(best, second, __int_as_float(kbest), 0.f);

@@ -6,7 +6,9 @@ Tolerances (stated for the FP32 GPU path against the FP64 oracle):
   * per-superpixel cost / energy within REL = 1e-3 relative + ABS = 1e-6;
   * centroid depth within DEPTH_REL = 0.5 %.
 Where the margin is below MARGIN and the choices differ, the GPU's pick must
-score within MARGIN of the oracle's best under the oracle's own arithmetic.
+score within MARGIN of the oracle's best under the oracle's own arithmetic, and
+its cost or energy and its centroid depth must match the oracle's for that same
+level or slot.
 """
 from __future__ import annotations
 
@@ -109,16 +111,16 @@ def check_refine(orc, ctx, A64, it, B_o=None, E_o=None, K_o=None, M_o=None, samp
         pe = np.sort(ens[prop])[::-1]
         prop_margin = pe[0] - pe[1] if len(pe) > 1 else np.inf
         if prop_margin > MARGIN:
-            outcomes = [(k_o, e_o, pl_o, slots, ens)]
+            outcomes = [(k_o, e_o, pl_o, slots, planes, ens)]
         else:  # the pivot itself is a near-tie: every tied propagation candidate may pivot
             rep["pivot_ties"] += 1
             outcomes = []
             for c in slots[prop][ens[prop] >= pe[0] - MARGIN]:
-                pl_c, e_c, k_c, sl_c, _, en_c = orc.refine_pivot(A64, it, v, s, int(c))
-                outcomes.append((k_c, e_c, pl_c, sl_c, en_c))
+                pl_c, e_c, k_c, sl_c, pls_c, en_c = orc.refine_pivot(A64, it, v, s, int(c))
+                outcomes.append((k_c, e_c, pl_c, sl_c, pls_c, en_c))
         ok = False
         why = ""
-        for k_c, e_c, pl_c, sl_c, en_c in outcomes:
+        for k_c, e_c, pl_c, sl_c, pls_c, en_c in outcomes:
             if k_g == k_c:
                 if close(e_g, e_c) and abs(P_g[g, 0] - pl_c[0]) <= DEPTH_REL * pl_c[0]:
                     ok = True
@@ -130,10 +132,12 @@ def check_refine(orc, ctx, A64, it, B_o=None, E_o=None, K_o=None, M_o=None, samp
                 why = why or "GPU slot %d not among the oracle's candidates" % k_g
                 continue
             e_at = en_c[hit[-1]]
-            if e_c - e_at <= MARGIN and close(e_g, e_at):
+            d_at = pls_c[hit[-1]][0]  # the oracle's plane for the GPU's slot: its depth must match too
+            if e_c - e_at <= MARGIN and close(e_g, e_at) and abs(P_g[g, 0] - d_at) <= DEPTH_REL * d_at:
                 ok = True
                 break
-            why = "slot %d (E %.9g, oracle there %.9g) vs oracle slot %d (E %.9g)" % (k_g, e_g, e_at, k_c, e_c)
+            why = "slot %d (E %.9g, depth %.7g; oracle there E %.9g, depth %.7g) vs oracle slot %d (E %.9g)" % (
+                k_g, e_g, P_g[g, 0], e_at, d_at, k_c, e_c)
         if ok:
             rep["near_tie_flips"] += 1
         else:

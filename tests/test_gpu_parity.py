@@ -259,6 +259,32 @@ def test_refine_lockstep_term_ablations(mask):
     _lockstep(w, 1)
 
 
+@pytest.mark.parametrize("occ_tol", [0.0, 1e-3])
+def test_refine_lockstep_literal_and_tolerant_visibility_split(occ_tol):
+    """Eqs. (10)-(11) split the samples into visible (X) and occluded (Y) by
+    comparing depths; tau = 0 is the literal comparison, tau = 1e-3 the default
+    tolerance.  Both run in lockstep against the oracle on a slanted state,
+    where consistent surfaces put many samples at z = D(p^i) up to rounding."""
+    from lfsynth import random_planes
+
+    _say("refine lockstep occ_tol %g" % occ_tol)
+    w = config1()
+    w.params.occ_tol = occ_tol
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    for start in ("sweep", "slanted"):
+        if start == "sweep":
+            A64 = parity.round_state(orc.sweep()[0])
+        else:
+            rng = np.random.default_rng(17)
+            A64 = parity.round_state(np.concatenate([random_planes(rng, v.gw, v.gh, 2.0, 8.0) for v in w.rig.views]))
+        for v in range(orc.V):
+            ctx.set_planes(v, A64[orc.view_slice(v)])
+        ctx.propagate(1, 1)
+        rep = parity.check_refine(orc, ctx, A64, 1)
+        _assert_clean(rep, "refine occ_tol %g from the %s state" % (occ_tol, start))
+
+
 def test_refine_lockstep_data_only_mode():
     _say("refine lockstep data-only energy")
     w = config1()
