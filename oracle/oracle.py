@@ -13,7 +13,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "slfo.c")
+_SRCS = [os.path.join(_HERE, "slfo.c"), os.path.join(_HERE, "slfo_fuse.c")]
 _OUT_DIR = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_OUT_DIR, "libslfo.so")
 _lib = None
@@ -23,7 +23,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(_OUT_DIR, exist_ok=True)
     tmp = _LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-           "-Wall", "-Wextra", "-Wno-unused-parameter", _SRC, "-o", tmp, "-lm"]
+           "-Wall", "-Wextra", "-Wno-unused-parameter", *_SRCS, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
@@ -81,6 +81,9 @@ def lib():
         L.slfo_refine_trace.argtypes = [P, P, I, I, I, P, P, P, I]
         L.slfo_refine_pivot.argtypes = [P, P, I, I, I, I, P, P, P, P, P, P, I]
         L.slfo_render_depth.argtypes = [P, P, I, P]
+        L.slfo_fuse_project.argtypes = [I, P, P, P, P, P, I, I, P]
+        L.slfo_fuse_vote.argtypes = [I, P, ctypes.c_float, P]
+        L.slfo_fuse_view.argtypes = [I, P, P, P, P, P, I, ctypes.c_float, P, P, P, P]
         _lib = L
     return _lib
 
@@ -135,6 +138,57 @@ def warm_start_planes(Kinv, cen_prev, area_prev, A_prev, cen_new, area_new, d_mi
                 continue
         out[g] = [d_fb, 0.0, 0.0, 1.0]
     return out
+
+
+class FusionCams:
+    """Cameras of a rig for the fusion oracle (Sec. III-D): any sequence of views
+    with W, H, K (3x3), R (3x3), t (3)."""
+
+    def __init__(self, views):
+        self.V = len(views)
+        self.wh = np.ascontiguousarray([[int(v.W), int(v.H)] for v in views], np.int32)
+        self.K = np.ascontiguousarray(np.stack([np.asarray(v.K, np.float64).reshape(9) for v in views]))
+        self.R = np.ascontiguousarray(np.stack([np.asarray(v.R, np.float64).reshape(9) for v in views]))
+        self.t = np.ascontiguousarray(np.stack([np.asarray(v.t, np.float64).reshape(3) for v in views]))
+
+    def _depth(self, depths):
+        if len(depths) != self.V:
+            raise ValueError("need one depth map per view")
+        for v, d in enumerate(depths):
+            if np.shape(d) != (self.wh[v, 1], self.wh[v, 0]):
+                raise ValueError("depth map %d has shape %s" % (v, np.shape(d)))
+        return np.ascontiguousarray(np.concatenate([np.asarray(d, np.float32).reshape(-1) for d in depths]))
+
+    def project(self, depths, ref, src):
+        """Pass 1: candidate depths of view `src` at the pixels of view `ref` (0 = none)."""
+        D = self._depth(depths)
+        W, H = self.wh[ref]
+        out = np.empty((H, W), np.float32)
+        if lib().slfo_fuse_project(self.V, _p(self.wh), _p(self.K), _p(self.R), _p(self.t), _p(D), ref, src,
+                                   _p(out)):
+            raise ValueError("bad views")
+        return out
+
+    def fuse(self, depths, ref, tau):
+        """Both passes for view `ref`: (fused, winner view, winner stability, candidate count)."""
+        D = self._depth(depths)
+        W, H = self.wh[ref]
+        fused = np.empty((H, W), np.float32)
+        win = np.empty((H, W), np.int32)
+        stab = np.empty((H, W), np.int32)
+        nc = np.empty((H, W), np.int32)
+        if lib().slfo_fuse_view(self.V, _p(self.wh), _p(self.K), _p(self.R), _p(self.t), _p(D), ref,
+                                float(tau), _p(fused), _p(win), _p(stab), _p(nc)):
+            raise ValueError("bad arguments")
+        return fused, win, stab, nc
+
+
+def fuse_vote(cands, tau):
+    """Pass 2 on one pixel: (winner index or -1, stability per candidate)."""
+    c = np.ascontiguousarray(cands, np.float32)
+    s = np.empty(len(c), np.int32)
+    b = lib().slfo_fuse_vote(len(c), _p(c), ctypes.c_float(tau), _p(s))
+    return int(b), s
 
 
 class Oracle:

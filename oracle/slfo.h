@@ -108,6 +108,29 @@ int slfo_refine_pivot(const slfo_ctx *c, const double *A, int iter, int view, in
 /* per-pixel depth of view `view` from planes [S][4]; 0 where undefined */
 int slfo_render_depth(const slfo_ctx *c, const double *planes, int view, double *out);
 
+/* Stability-based depth fusion (Sec. III-D; two passes per reference view,
+ * Sec. III-E).  Cameras as in slfo_rig: wh [V][2], K, R [V][9], t [V][3];
+ * depth: FP32 depth maps of all views concatenated (H x W each, <= 0 = none).
+ *
+ * slfo_fuse_project: pass 1 for one (reference, source) pair: cand [H_r][W_r]
+ * receives, per reference pixel, the smallest camera-r depth of the source
+ * pixels whose 3D points project to it (nearest pixel, round half up), 0 if
+ * none.
+ * slfo_fuse_vote: pass 2 on one pixel: candidates c[n] (0 = none) in view
+ * order; stability[j] = #agreeing - #disagreeing other non-zero candidates,
+ * agreement |c_k - c_j| <= tau c_j in FP32; returns the index of the smallest
+ * candidate with stability >= 0 (equal depths: smaller index) or -1.
+ * slfo_fuse_view: both passes for reference view `ref` (the reference's own
+ * depth is its candidate); fused [H_r][W_r]; winner (view index or -1),
+ * stability (the winner's, 0 if none) and n_cand (non-zero candidates) may
+ * be NULL.  V <= 64. */
+int slfo_fuse_project(int n_views, const int32_t *wh, const double *K, const double *R, const double *t,
+                      const float *depth, int ref, int src, float *cand);
+int slfo_fuse_vote(int n, const float *c, float tau, int32_t *stability);
+int slfo_fuse_view(int n_views, const int32_t *wh, const double *K, const double *R, const double *t,
+                   const float *depth, int ref, float tau, float *fused, int32_t *winner, int32_t *stability,
+                   int32_t *n_cand);
+
 #ifdef __cplusplus
 }
 #endif
