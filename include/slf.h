@@ -228,6 +228,46 @@ int slf_warm_start(slf_ctx *ctx);
  * labels are set. */
 int slf_get_footprint(slf_ctx *ctx, uint64_t *bytes);
 
+/* Stability-based depth fusion (Sec. III-D), the two passes per reference
+ * view of Sec. III-E run for every view at once.  Pass 1: each pixel of every
+ * view with a depth is lifted to its 3D point and projected into every other
+ * view; the nearest pixel (round half up) of that reference receives the
+ * point's depth in the reference camera as this view's candidate, the closest
+ * point winning when several land on one pixel.  Pass 2: at each reference
+ * pixel the candidates are its own depth and one per other view; a non-zero
+ * candidate c_j gains one for every other non-zero candidate c_k with
+ * |c_k - c_j| <= agree_tol c_j and loses one for every other; the fused depth
+ * is the smallest candidate whose stability is >= 0 (equal depths: the
+ * smaller view index), 0 where there is none.  Depth maps and candidates are
+ * FP32; the projection is FP64 as one fixed sequence of correctly rounded
+ * operations (ray by Cramer's rule on K's upper 2 x 2 block, world point, the
+ * reference's camera, projection); the agreement test is FP32.
+ *
+ * slf_fuse: fuses the depth maps of the current planes of all views (those
+ * slf_get_depth returns) and keeps the result in the context.  Needs planes
+ * for every view (SLF_ESTATE).  agree_tol >= 0, finite (SLF_EINVAL); at most
+ * 64 views (SLF_EUNSUPPORTED).  On first use it allocates 12 bytes per pixel
+ * plus 4 (V - 1) bytes per pixel of candidate layers; these are not part of
+ * slf_get_footprint.  Asynchronous. */
+int slf_fuse(slf_ctx *ctx, float agree_tol);
+/* Fused depth of a view after slf_fuse: H rows separated by row_stride_elems
+ * (>= W) into out (may be NULL), and, if votes is not NULL, the pass-2 record
+ * of each pixel in the same layout: bits 0-7 the winning view (255: none),
+ * bits 8-15 the number of non-zero candidates, bits 16-31 the winner's
+ * stability as a signed 16-bit value (0 if none).  is_device = 1: out and
+ * votes are device buffers written asynchronously; 0: host buffers, the call
+ * synchronises.  SLF_ESTATE before slf_fuse. */
+int slf_get_fused_depth(slf_ctx *ctx, int view, float *out, int64_t row_stride_elems, int32_t *votes, int is_device);
+/* The same fusion on caller depth maps: depth[v], fused[v] (and votes[v] if
+ * votes is not NULL, layout as above) are device buffers of H_v x W_v values
+ * (row stride W_v) for every view v of the context's cameras; depths <= 0,
+ * NaN or inf are no depth.  Only the cameras need to be set (SLF_ESTATE).
+ * The candidate layers (4 (V - 1) bytes per pixel) are the context's,
+ * allocated on first use.  Asynchronous on the context's stream: the caller
+ * keeps the buffers alive until it completes. */
+int slf_fuse_depth(slf_ctx *ctx, const float *const *depth, float *const *fused, int32_t *const *votes,
+                   float agree_tol);
+
 const char *slf_status_string(int status);
 /* Message of the last failing call on ctx ("" if none); valid until the next call. */
 const char *slf_last_error(const slf_ctx *ctx);

@@ -10,7 +10,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libslf.so")
-SOURCES = ["slf_api.hip", "slf_kernels.hip", "slf_pool.hip"]
+SOURCES = ["slf_api.hip", "slf_kernels.hip", "slf_pool.hip", "slf_fusion.hip"]
+# the fusion's FP64 projection is one fixed sequence of correctly rounded operations
+EXTRA_FLAGS = {"slf_fusion.hip": ["-ffp-contract=off"]}
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -28,7 +30,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
-        cmd = [hipcc, *HIPCC_FLAGS, "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-x", "hip", "-c",
+        cmd = [hipcc, *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-x", "hip", "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -125,6 +125,10 @@ void free_all(slf_ctx *c) {
   dfree(c->d_work);
   dfree(c->d_claims);
   dfree(c->d_depth_tmp);
+  for (void **f : {&c->d_fz, &c->d_fcams, &c->d_fdepth, &c->d_fused, &c->d_fvotes}) dfree(*f);
+  c->fz_bytes = c->fcams_bytes = c->fdepth_bytes = c->fused_bytes = c->fvotes_bytes = 0;
+  c->fcams_h.clear();
+  c->has_fused = false;
 }
 
 bool views_ready(const slf_ctx *c) {
@@ -586,6 +590,7 @@ int slf_set_cameras(slf_ctx *c, int n_views, const int32_t *wh, const double *K,
   c->sp_dirty = true;
   c->quads_dirty = true;
   c->S = 0;
+  c->has_fused = false;
   return SLF_OK;
 }
 

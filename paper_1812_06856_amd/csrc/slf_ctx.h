@@ -78,6 +78,13 @@ struct slf_ctx {
   int n_cu = 0;             // compute units of the device
   float *d_depth_tmp = nullptr;
   int64_t depth_tmp_n = 0;
+  // depth fusion (slf_fusion.hip), allocated on first use: candidate layers,
+  // the device camera table (and its host copy), the depth maps read out of
+  // the planes, the fused depth and the votes
+  void *d_fz = nullptr, *d_fcams = nullptr, *d_fdepth = nullptr, *d_fused = nullptr, *d_fvotes = nullptr;
+  int64_t fz_bytes = 0, fcams_bytes = 0, fdepth_bytes = 0, fused_bytes = 0, fvotes_bytes = 0;
+  std::vector<unsigned char> fcams_h;
+  bool has_fused = false;
   int cur = 0;
   std::vector<int> area_h;
   std::vector<double2> cen_h;

@@ -25,6 +25,7 @@ EXPORTED = [
     "slf_set_neighbors", "slf_set_image_rgb8", "slf_set_labels", "slf_prepare", "slf_sweep", "slf_set_planes", "slf_propagate",
     "slf_get_planes", "slf_get_depth", "slf_get_superpixels", "slf_get_work", "slf_get_sweep_work", "slf_reset_work", "slf_synchronize",
     "slf_status_string", "slf_last_error", "slf_warm_start", "slf_get_footprint",
+    "slf_fuse", "slf_get_fused_depth", "slf_fuse_depth",
     "slf_pool_default_config", "slf_pool_create", "slf_pool_destroy", "slf_pool_set_stream", "slf_pool_set_config",
     "slf_pool_get_config", "slf_pool_attach", "slf_pool_detach", "slf_pool_usage", "slf_pool_submit", "slf_pool_step",
     "slf_pool_run", "slf_pool_poll", "slf_pool_synchronize", "slf_pool_autotune", "slf_pool_last_error",
@@ -93,6 +94,9 @@ def load(path: str = LIB_PATH):
     U64, PU64, PI = ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int)
     L.slf_warm_start.argtypes = [P]
     L.slf_get_footprint.argtypes = [P, PU64]
+    L.slf_fuse.argtypes = [P, ctypes.c_float]
+    L.slf_get_fused_depth.argtypes = [P, I, P, I64, P, I]
+    L.slf_fuse_depth.argtypes = [P, P, P, P, ctypes.c_float]
     L.slf_pool_default_config.argtypes = [ctypes.POINTER(slf_pool_config)]
     L.slf_pool_default_config.restype = None
     L.slf_pool_create.argtypes = [I, U64, ctypes.POINTER(P)]
@@ -311,6 +315,40 @@ class Context:
         b = ctypes.c_uint64()
         self._check(self._L.slf_get_footprint(self._h, ctypes.byref(b)))
         return int(b.value)
+
+    # -- depth fusion
+    def fuse(self, agree_tol: float = 0.01) -> None:
+        self._check(self._L.slf_fuse(self._h, float(agree_tol)))
+
+    def get_fused_depth(self, view: int, out: Optional[torch.Tensor] = None, votes: Optional[torch.Tensor] = None):
+        """Host: returns (fused [H, W] float32, votes [H, W] int32).  Device: fills
+        the given tensors (row stride of `out`, or of `votes` if out is None)."""
+        W, H = self.dims[view]
+        if out is not None or votes is not None:
+            ref = out if out is not None else votes
+            for tsr in (out, votes):
+                assert tsr is None or (tsr.is_cuda and tsr.stride(1) == 1 and tsr.stride(0) == ref.stride(0))
+            self._check(self._L.slf_get_fused_depth(self._h, view, None if out is None else _ptr(out), ref.stride(0),
+                                                    None if votes is None else _ptr(votes), 1))
+            return out, votes
+        a = np.empty((H, W), np.float32)
+        v = np.empty((H, W), np.int32)
+        self._check(self._L.slf_get_fused_depth(self._h, view, _ptr(a), W, _ptr(v), 0))
+        return a, v
+
+    def fuse_depth(self, depth: Sequence[torch.Tensor], fused: Sequence[torch.Tensor],
+                   votes: Optional[Sequence[torch.Tensor]] = None, agree_tol: float = 0.01) -> None:
+        """Fusion of caller depth maps: device float32 tensors [H_v, W_v] (contiguous) per view."""
+        V = len(self.dims)
+        assert len(depth) == V and len(fused) == V and (votes is None or len(votes) == V)
+        for v in range(V):
+            W, H = self.dims[v]
+            for tsr, dt in ((depth[v], torch.float32), (fused[v], torch.float32)) + (
+                    ((votes[v], torch.int32),) if votes is not None else ()):
+                assert tsr.is_cuda and tsr.dtype == dt and tuple(tsr.shape) == (H, W) and tsr.is_contiguous()
+        arr = lambda ts: (ctypes.c_void_p * V)(*[t.data_ptr() for t in ts])
+        dv = arr(votes) if votes is not None else None
+        self._check(self._L.slf_fuse_depth(self._h, arr(depth), arr(fused), dv, float(agree_tol)))
 
     def reset_work(self) -> None:
         self._check(self._L.slf_reset_work(self._h))
