@@ -268,6 +268,23 @@ int slf_get_fused_depth(slf_ctx *ctx, int view, float *out, int64_t row_stride_e
 int slf_fuse_depth(slf_ctx *ctx, const float *const *depth, float *const *fused, int32_t *const *votes,
                    float agree_tol);
 
+/* slf_fuse_depth for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results as slf_fuse_depth, run one reference view at a time, with
+ * the camera table and that view's candidate layers in a fixed device array of
+ * 64 MiB that the library holds on each device it runs on until the process
+ * ends.  The call allocates nothing (no hipMalloc, no host-pinned memory); the
+ * caller still passes the depth, fused and votes buffers.  Each view v needs
+ * 4 (V - 1) W_v H_v <= 64 MiB - 16 KiB bytes of layers (about 16.7 M entries:
+ * 8 views of 1920 x 1080 or 16 views of 1280 x 720 fit), else SLF_EUNSUPPORTED
+ * before anything runs.  Every call on a device shares that device's array and
+ * leaves its last contents there; each call clears what it reads, but calls
+ * that overlap on one device (other streams, other contexts, other threads)
+ * race and give undefined results.  Asynchronous on the context's stream;
+ * other errors as slf_fuse_depth. */
+int slf_fuse_depth_static(slf_ctx *ctx, const float *const *depth, float *const *fused, int32_t *const *votes,
+                          float agree_tol);
+
 const char *slf_status_string(int status);
 /* Message of the last failing call on ctx ("" if none); valid until the next call. */
 const char *slf_last_error(const slf_ctx *ctx);

@@ -494,7 +494,7 @@ int slf_create(int device_ordinal, slf_ctx **out) {
     return SLF_ENOMEM;
   }
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device_ordinal) != hipSuccess ||
-      c->n_cu < 1) {
+      c->n_cu < 1 || static_scratch_init(device_ordinal) != SLF_OK) {
     free_all(c);
     delete c;
     return SLF_EDEVICE;

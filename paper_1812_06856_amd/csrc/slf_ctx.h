@@ -129,5 +129,8 @@ void after_sweep(slf_ctx *c);
 void after_refine(slf_ctx *c);
 // SLF_ESTATE when the rig has pool stages not yet launched.
 int check_idle(slf_ctx *c);
+// Takes the device address of the static fusion scratch on `device` (which
+// must be current), once per device; SLF_OK, SLF_EDEVICE or SLF_EUNSUPPORTED.
+int static_scratch_init(int device);
 
 }  // namespace slf

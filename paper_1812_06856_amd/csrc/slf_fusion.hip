@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "slf_ctx.h"
@@ -52,6 +53,15 @@ struct FuseView {
   float *fused;        // H x W
   int *votes;          // H x W or null
 };
+
+// Fixed device scratch of slf_fuse_depth_static (callers that cannot
+// allocate): the camera table, then the candidate layers of one reference
+// view.  Each device holds its own copy until the process ends.
+constexpr int64_t kStaticScratchBytes = 64ll << 20;
+constexpr int64_t kStaticTableBytes = 16 << 10;
+constexpr int64_t kStaticLayerBytes = kStaticScratchBytes - kStaticTableBytes;
+static_assert(sizeof(FuseView) * kFuseMaxViews <= kStaticTableBytes, "camera table does not fit");
+constexpr int kMaxDevices = 64;
 
 __global__ __launch_bounds__(256) void k_fuse_clear(uint32_t *z, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -102,6 +112,17 @@ __global__ __launch_bounds__(256) void k_fuse_project(const FuseView *__restrict
     uint32_t *slot = z + base + (int64_t)layer * Rv.W * Rv.H + (int64_t)(int)fv * Rv.W + (int)fu;
     atomicMin(slot, __float_as_uint(zf));
   }
+}
+
+// Writes up to kTableChunk table entries passed by value (the launch copies
+// its arguments, so no host buffer has to outlive the call).
+constexpr int kTableChunk = 8;
+struct TableChunk {
+  FuseView v[kTableChunk];
+};
+__global__ void k_fuse_put_table(FuseView *dst, TableChunk chunk, int n) {
+  const int k = threadIdx.x;
+  if (k < n) dst[k] = chunk.v[k];
 }
 
 __device__ inline float own_depth(float d) { return (d > 0.f && !isinf(d)) ? d : 0.f; }
@@ -171,9 +192,9 @@ __global__ __launch_bounds__(256) void k_fuse_vote(const FuseView *__restrict__ 
 // candidate-layer offsets for the all-references pass.  Returns the number of
 // candidate entries that pass needs.
 int64_t fuse_table(const slf_ctx *c, const float *const *depth, float *const *fused, int32_t *const *votes,
-                   std::vector<FuseView> &tab) {
+                   FuseView *tab) {
   const int V = c->V;
-  tab.assign(V, FuseView{});
+  for (int r = 0; r < V; ++r) tab[r] = FuseView{};
   int64_t off = 0;
   for (int r = 0; r < V; ++r) {
     const ViewHost &h = c->vh[r];
@@ -192,9 +213,9 @@ int64_t fuse_table(const slf_ctx *c, const float *const *depth, float *const *fu
   return off;
 }
 
-int max_pixels(const std::vector<FuseView> &tab) {
+int max_pixels(const FuseView *tab, int V) {
   int64_t m = 1;
-  for (const auto &f : tab) m = std::max<int64_t>(m, (int64_t)f.W * f.H);
+  for (int r = 0; r < V; ++r) m = std::max<int64_t>(m, (int64_t)tab[r].W * tab[r].H);
   return (int)m;
 }
 
@@ -215,7 +236,7 @@ hipError_t launch_vote(const FuseView *d_tab, int V, int ref, const uint32_t *z,
 hipError_t fuse_all(const FuseView *d_tab, const std::vector<FuseView> &tab, uint32_t *z, int64_t nz, float tau,
                     hipStream_t st) {
   const int V = (int)tab.size();
-  const int64_t maxP = max_pixels(tab);
+  const int64_t maxP = max_pixels(tab.data(), V);
   hipLaunchKernelGGL(k_fuse_clear, dim3((unsigned)std::min<int64_t>((nz + 255) / 256, 65536)), dim3(256), 0, st, z,
                      nz);
   hipLaunchKernelGGL(k_fuse_project, dim3((unsigned)((maxP + 255) / 256), (unsigned)V), dim3(256), 0, st, d_tab, V,
@@ -263,8 +284,8 @@ int upload_table(slf_ctx *c, const std::vector<FuseView> &tab) {
 // Runs both passes for the given device buffers with buffers the context owns
 // (candidate layers and the device table).
 int fuse_into(slf_ctx *c, const float *const *depth, float *const *fused, int32_t *const *votes, float tau) {
-  std::vector<FuseView> tab;
-  const int64_t nz = fuse_table(c, depth, fused, votes, tab);
+  std::vector<FuseView> tab(c->V);
+  const int64_t nz = fuse_table(c, depth, fused, votes, tab.data());
   int rc;
   if ((rc = grow(c, (void **)&c->d_fz, &c->fz_bytes, nz * (int64_t)sizeof(uint32_t)))) return rc;
   if ((rc = upload_table(c, tab))) return rc;
@@ -274,6 +295,35 @@ int fuse_into(slf_ctx *c, const float *const *depth, float *const *fused, int32_
 
 }  // namespace
 }  // namespace slf
+
+// The scratch itself.  Host code never passes `scratch` to a kernel or a copy:
+// on the host the name stands in for the symbol, not for a device address.
+// Its address on each device is taken once, at context creation with that
+// device current, and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[slf::kStaticScratchBytes];
+
+namespace {
+std::mutex scratch_mu;
+void *scratch_ptr[slf::kMaxDevices] = {};
+}  // namespace
+
+int slf::static_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return SLF_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_ptr[device]) return SLF_OK;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SLF_EDEVICE;
+  scratch_ptr[device] = p;
+  return SLF_OK;
+}
+
+namespace {
+void *static_scratch(int device) {
+  if (device < 0 || device >= slf::kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  return scratch_ptr[device];
+}
+}  // namespace
 
 using namespace slf;
 
@@ -341,6 +391,49 @@ int slf_fuse_depth(slf_ctx *c, const float *const *depth, float *const *fused, i
   }
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   return fuse_into(c, depth, fused, votes, agree_tol);
+}
+
+int slf_fuse_depth_static(slf_ctx *c, const float *const *depth, float *const *fused, int32_t *const *votes,
+                          float agree_tol) {
+  if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
+  if (int rc = check_fuse_args(c, agree_tol)) return rc;
+  if (!depth || !fused) return c->fail(SLF_EINVAL, "depth and fused must not be NULL");
+  for (int v = 0; v < c->V; ++v) {
+    if (!depth[v] || !fused[v]) return c->fail(SLF_EINVAL, "depth or fused buffer of view %d is NULL", v);
+    if (votes && !votes[v]) return c->fail(SLF_EINVAL, "votes buffer of view %d is NULL", v);
+    const int64_t need = (int64_t)(c->V - 1) * c->vh[v].W * c->vh[v].H * (int64_t)sizeof(uint32_t);
+    if (need > kStaticLayerBytes)
+      return c->fail(SLF_EUNSUPPORTED, "view %d needs %lld bytes of candidate layers, above the %lld of the static scratch",
+                     v, (long long)need, (long long)kStaticLayerBytes);
+  }
+  unsigned char *base = (unsigned char *)static_scratch(c->device);
+  if (!base) return c->fail(SLF_EDEVICE, "static scratch of device %d not set up", c->device);
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  FuseView tab[kFuseMaxViews];  // host copy on the stack: the call allocates nothing
+  fuse_table(c, depth, fused, votes, tab);
+  FuseView *d_tab = (FuseView *)base;
+  uint32_t *z = (uint32_t *)(base + kStaticTableBytes);
+  const int V = c->V;
+  for (int k0 = 0; k0 < V; k0 += kTableChunk) {
+    TableChunk ch{};
+    const int n = std::min(kTableChunk, V - k0);
+    for (int k = 0; k < n; ++k) ch.v[k] = tab[k0 + k];
+    hipLaunchKernelGGL(k_fuse_put_table, dim3(1), dim3(64), 0, c->stream, d_tab + k0, ch, n);
+  }
+  HIP_OR_FAIL(c, hipGetLastError());
+  const int64_t maxP = max_pixels(tab, V);
+  // one reference view at a time: its candidate layers fill the scratch
+  for (int r = 0; r < V; ++r) {
+    const int64_t P = (int64_t)tab[r].W * tab[r].H;
+    const int64_t nz = (int64_t)(V - 1) * P;
+    hipLaunchKernelGGL(k_fuse_clear, dim3((unsigned)std::min<int64_t>((nz + 255) / 256, 65536)), dim3(256), 0,
+                       c->stream, z, nz);
+    hipLaunchKernelGGL(k_fuse_project, dim3((unsigned)((maxP + 255) / 256), (unsigned)V), dim3(256), 0, c->stream,
+                       (const FuseView *)d_tab, V, r, z);
+    HIP_OR_FAIL(c, launch_vote(d_tab, V, r, z, agree_tol, P, 1, c->stream));
+  }
+  return SLF_OK;
 }
 
 }  // extern "C"

@@ -25,7 +25,7 @@ EXPORTED = [
     "slf_set_neighbors", "slf_set_image_rgb8", "slf_set_labels", "slf_prepare", "slf_sweep", "slf_set_planes", "slf_propagate",
     "slf_get_planes", "slf_get_depth", "slf_get_superpixels", "slf_get_work", "slf_get_sweep_work", "slf_reset_work", "slf_synchronize",
     "slf_status_string", "slf_last_error", "slf_warm_start", "slf_get_footprint",
-    "slf_fuse", "slf_get_fused_depth", "slf_fuse_depth",
+    "slf_fuse", "slf_get_fused_depth", "slf_fuse_depth", "slf_fuse_depth_static",
     "slf_pool_default_config", "slf_pool_create", "slf_pool_destroy", "slf_pool_set_stream", "slf_pool_set_config",
     "slf_pool_get_config", "slf_pool_attach", "slf_pool_detach", "slf_pool_usage", "slf_pool_submit", "slf_pool_step",
     "slf_pool_run", "slf_pool_poll", "slf_pool_synchronize", "slf_pool_autotune", "slf_pool_last_error",
@@ -97,6 +97,7 @@ def load(path: str = LIB_PATH):
     L.slf_fuse.argtypes = [P, ctypes.c_float]
     L.slf_get_fused_depth.argtypes = [P, I, P, I64, P, I]
     L.slf_fuse_depth.argtypes = [P, P, P, P, ctypes.c_float]
+    L.slf_fuse_depth_static.argtypes = [P, P, P, P, ctypes.c_float]
     L.slf_pool_default_config.argtypes = [ctypes.POINTER(slf_pool_config)]
     L.slf_pool_default_config.restype = None
     L.slf_pool_create.argtypes = [I, U64, ctypes.POINTER(P)]
@@ -337,8 +338,10 @@ class Context:
         return a, v
 
     def fuse_depth(self, depth: Sequence[torch.Tensor], fused: Sequence[torch.Tensor],
-                   votes: Optional[Sequence[torch.Tensor]] = None, agree_tol: float = 0.01) -> None:
-        """Fusion of caller depth maps: device float32 tensors [H_v, W_v] (contiguous) per view."""
+                   votes: Optional[Sequence[torch.Tensor]] = None, agree_tol: float = 0.01,
+                   static_scratch: bool = False) -> None:
+        """Fusion of caller depth maps: device float32 tensors [H_v, W_v] (contiguous) per view.
+        static_scratch: slf_fuse_depth_static (no allocation; the library's fixed scratch)."""
         V = len(self.dims)
         assert len(depth) == V and len(fused) == V and (votes is None or len(votes) == V)
         for v in range(V):
@@ -348,7 +351,8 @@ class Context:
                 assert tsr.is_cuda and tsr.dtype == dt and tuple(tsr.shape) == (H, W) and tsr.is_contiguous()
         arr = lambda ts: (ctypes.c_void_p * V)(*[t.data_ptr() for t in ts])
         dv = arr(votes) if votes is not None else None
-        self._check(self._L.slf_fuse_depth(self._h, arr(depth), arr(fused), dv, float(agree_tol)))
+        fn = self._L.slf_fuse_depth_static if static_scratch else self._L.slf_fuse_depth
+        self._check(fn(self._h, arr(depth), arr(fused), dv, float(agree_tol)))
 
     def reset_work(self) -> None:
         self._check(self._L.slf_reset_work(self._h))
