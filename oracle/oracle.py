@@ -76,6 +76,8 @@ def lib():
         L.slfo_sweep_all.argtypes = [P, P, P, P, P]
         L.slfo_energy.argtypes = [P, P, I, I, P]
         L.slfo_energy.restype = D
+        L.slfo_energy_flip_bound.argtypes = [P, P, I, I, P, D, D]
+        L.slfo_energy_flip_bound.restype = D
         L.slfo_refine_sp.argtypes = [P, P, I, I, I, P, P, P, P]
         L.slfo_refine_all.argtypes = [P, P, I, P, P, P, P]
         L.slfo_refine_trace.argtypes = [P, P, I, I, I, P, P, P, I]
@@ -287,6 +289,13 @@ class Oracle:
         A = np.ascontiguousarray(A, np.float64)
         pl = np.ascontiguousarray(plane, np.float64)
         return float(self._L.slfo_energy(self._c, _p(A), view, sp, _p(pl)))
+
+    def energy_flip_bound(self, A, view, sp, plane, eps_px=1e-4, eps_rel=1e-5):
+        """Upper bound of the energy change from flipping sample decisions that
+        lie within eps_px / eps_rel of their thresholds (parity instrument)."""
+        A = np.ascontiguousarray(A, np.float64)
+        pl = np.ascontiguousarray(plane, np.float64)
+        return float(self._L.slfo_energy_flip_bound(self._c, _p(A), view, sp, _p(pl), eps_px, eps_rel))
 
     def refine_sp(self, A, it, view, sp):
         A = np.ascontiguousarray(A, np.float64)

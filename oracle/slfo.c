@@ -553,6 +553,79 @@ static double energy_nd(const slfo_ctx *c, const double *A, int r, int s, const 
     return Ec * Es;
 }
 
+/* Parity instrument, not part of the method.  The consistency term takes two
+ * discrete decisions per sample: the nearest pixel of view i (eq. 9, round
+ * half up, which also decides whether the sample is inside view i) and the
+ * visible / occluded split (eqs. 10-11).  An implementation that forms x, y
+ * or z in lower precision may take either side of a decision whose value lies
+ * within its rounding of the threshold.  This returns an upper bound of how
+ * much E (eq. 3) can change when any such decisions flip: per view, k samples
+ * within eps_px of a rounding threshold or within eps_rel (relative) of the
+ * split change S_i by at most k / |Omega| (omega in [0, 1]) and the mean of
+ * the X samples' Gaussians by at most k / max(|X| - k, 1), so V_i by at most
+ * their sum; O_i can toggle if |Y| <= k; E_c averages the views and E
+ * multiplies E_s.  Returns 0 when no decision is that close. */
+double slfo_energy_flip_bound(const slfo_ctx *c, const double *A, int r, int s, const double plane[4], double eps_px,
+                              double eps_rel)
+{
+    if (r < 0 || r >= c->V || s < 0 || s >= c->sp_off[r + 1] - c->sp_off[r]) return NAN;
+    int64_t g = gid(c, r, s);
+    if (c->area[g] == 0 || c->p.energy_mode == 1 || !(c->p.term_mask & 2u)) return 0.0;
+    const double *n = plane + 1;
+    double delta = plane_delta(c, r, s, plane);
+    int Wr = W_of(c, r);
+    double area = c->area[g];
+    double wmin = omega_min(c, r, s);
+    double total = 0.0;
+    for (int j = c->rig.nbr_off[r]; j < c->rig.nbr_off[r + 1]; ++j) {
+        int i = c->rig.nbr[j];
+        double H[9];
+        homography(c, r, i, n, delta, H);
+        int Wi = W_of(c, i), Hi = H_of(c, i);
+        const int32_t *lab_i = lab_of(c, i);
+        int64_t nX = 0, nY = 0, k = 0;
+        for (int64_t q = c->px_off[g]; q < c->px_off[g + 1]; ++q) {
+            int pix = c->px[q];
+            double pu = pix % Wr, pv = pix / Wr;
+            double ray[3];
+            backproject(c, r, pu, pv, ray);
+            double iota = dot3(n, ray) / delta;
+            if (!(iota > 0.0)) continue;
+            double D = 1.0 / iota;
+            double hp[3] = {H[0] * pu + H[1] * pv + H[2], H[3] * pu + H[4] * pv + H[5], H[6] * pu + H[7] * pv + H[8]};
+            if (!(hp[2] > 0.0)) continue;
+            double z = D * hp[2];
+            double x = hp[0] / hp[2], y = hp[1] / hp[2];
+            double fx = x + 0.5 - floor(x + 0.5), fy = y + 0.5 - floor(y + 0.5);
+            int near = fx < eps_px || fx > 1.0 - eps_px || fy < eps_px || fy > 1.0 - eps_px;
+            double ui = floor(x + 0.5), vi = floor(y + 0.5);
+            if (ui < 0.0 || ui > Wi - 1 || vi < 0.0 || vi > Hi - 1) {
+                k += near;
+                continue;
+            }
+            int l = lab_i[(int64_t)vi * Wi + (int64_t)ui];
+            int64_t gl = gid(c, i, l);
+            const double *pl = A + 4 * gl;
+            double dl = plane_delta(c, i, l, pl);
+            double rayi[3];
+            backproject(c, i, x, y, rayi);
+            double inv = dot3(pl + 1, rayi) / dl;
+            double Di = inv > 0.0 ? 1.0 / inv : INFINITY;
+            double lim = Di * (1.0 + c->p.occ_tol);
+            if (z <= lim) ++nX; else ++nY;
+            if (isfinite(lim) && fabs(z - lim) <= eps_rel * z) near = 1;
+            k += near;
+        }
+        if (k == 0) continue;
+        double b = (double)k / area + (double)k / (double)(nX - k > 1 ? nX - k : 1);
+        if (b > 1.0) b = 1.0;   /* V_i lies in [0, 1] */
+        if ((c->p.term_mask & 4u) && nY <= k) b += c->p.eta * (1.0 - wmin);
+        total += b;
+    }
+    double Es = (c->p.term_mask & 1u) ? e_smooth(c, A, r, s, n, delta) : 1.0;
+    return Es * total / n_nbr(c, r);
+}
+
 double slfo_energy(const slfo_ctx *c, const double *A, int r, int s, const double plane[4])
 {
     if (r < 0 || r >= c->V || s < 0 || s >= c->sp_off[r + 1] - c->sp_off[r]) return NAN;

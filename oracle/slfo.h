@@ -87,6 +87,13 @@ int slfo_sweep_all(const slfo_ctx *c, double *planes, double *cost, int32_t *cho
 /* energy (eq. 3) of stored plane `plane` for (view, sp) given state A [S][4] */
 double slfo_energy(const slfo_ctx *c, const double *A, int view, int sp, const double plane[4]);
 
+/* Parity instrument: an upper bound of the change of the energy of `plane`
+ * when sample decisions of eqs. (9)-(11) that lie within eps_px of a
+ * nearest-pixel threshold or within eps_rel of the visibility split flip; 0 if
+ * none is that close. */
+double slfo_energy_flip_bound(const slfo_ctx *c, const double *A, int view, int sp, const double plane[4],
+                              double eps_px, double eps_rel);
+
 /* one refinement iteration (propagation then normals, Jacobi in A -> B) */
 int slfo_refine_sp(const slfo_ctx *c, const double *A, int iter, int view, int sp, double plane[4],
                    double *energy, int32_t *choice, double *margin);

@@ -9,6 +9,15 @@ Where the margin is below MARGIN and the choices differ, the GPU's pick must
 score within MARGIN of the oracle's best under the oracle's own arithmetic, and
 its cost or energy and its centroid depth must match the oracle's for that same
 level or slot.
+
+The consistency energy takes discrete decisions per sample (the nearest pixel
+of eq. 9, the visible / occluded split of eqs. 10-11).  A decision whose value
+lies within FP32 rounding of its threshold may legitimately fall either way
+on the GPU.  Where the energies disagree, the oracle's bound of what flipping
+the decisions within FLIP_EPS_PX (nearest pixel) or FLIP_EPS_REL (split) of
+their thresholds can change (Oracle.energy_flip_bound) widens the energy
+tolerance and the margin of that candidate; it is 0 for candidates with no
+such decision.
 """
 from __future__ import annotations
 
@@ -18,6 +27,8 @@ MARGIN = 1e-4
 REL = 1e-3
 ABS = 1e-6
 DEPTH_REL = 5e-3
+FLIP_EPS_PX = 1e-4   # the GPU's nearest-pixel decision is exact to about 1e-6 px
+FLIP_EPS_REL = 1e-5  # its relative error of z and D(p^i) is about 1e-6
 
 
 def close(a, b, rel=REL, abs_=ABS):
@@ -89,7 +100,7 @@ def check_refine(orc, ctx, A64, it, B_o=None, E_o=None, K_o=None, M_o=None, samp
     area = orc.sp_stats()[0]
     if sample is None:
         sample = [(v, s) for v in range(orc.V) for s in range(int(orc.sp_off[v + 1] - orc.sp_off[v]))]
-    rep = {"n": 0, "mismatch_choice": 0, "near_tie_flips": 0, "pivot_ties": 0, "bad": []}
+    rep = {"n": 0, "mismatch_choice": 0, "near_tie_flips": 0, "pivot_ties": 0, "flip_bound_used": 0, "bad": []}
     for v, s in sample:
         g = int(orc.sp_off[v]) + s
         if area[g] == 0:
@@ -106,25 +117,39 @@ def check_refine(orc, ctx, A64, it, B_o=None, E_o=None, K_o=None, M_o=None, samp
         if k_g == k_o and close(e_g, e_o) and abs(P_g[g, 0] - pl_o[0]) <= DEPTH_REL * pl_o[0]:
             continue
         rep["mismatch_choice"] += k_g != k_o
+
+        def bound(plane, _v=v, _s=s):
+            return orc.energy_flip_bound(A64, _v, _s, plane, FLIP_EPS_PX, FLIP_EPS_REL)
+
         slots, planes, ens = orc.refine_trace(A64, it, v, s, cap=1024)
-        prop = slots < 1000
-        pe = np.sort(ens[prop])[::-1]
-        prop_margin = pe[0] - pe[1] if len(pe) > 1 else np.inf
-        if prop_margin > MARGIN:
+        prop = np.nonzero(slots < 1000)[0]
+        order = prop[np.argsort(-ens[prop], kind="stable")]
+        best = order[0]
+        prop_margin = ens[order[0]] - ens[order[1]] if len(order) > 1 else np.inf
+        b_best = bound(planes[best]) if prop_margin <= MARGIN + 1.0 else 0.0
+        tied = [int(slots[c]) for c in order[1:]
+                if ens[best] - ens[c] <= MARGIN + b_best + (bound(planes[c]) if ens[best] - ens[c] <= MARGIN + 1.0 else 0.0)]
+        if not tied:
             outcomes = [(k_o, e_o, pl_o, slots, planes, ens)]
         else:  # the pivot itself is a near-tie: every tied propagation candidate may pivot
             rep["pivot_ties"] += 1
             outcomes = []
-            for c in slots[prop][ens[prop] >= pe[0] - MARGIN]:
-                pl_c, e_c, k_c, sl_c, pls_c, en_c = orc.refine_pivot(A64, it, v, s, int(c))
+            for c in [int(slots[best])] + tied:
+                pl_c, e_c, k_c, sl_c, pls_c, en_c = orc.refine_pivot(A64, it, v, s, c)
                 outcomes.append((k_c, e_c, pl_c, sl_c, pls_c, en_c))
         ok = False
+        used_bound = False
         why = ""
         for k_c, e_c, pl_c, sl_c, pls_c, en_c in outcomes:
             if k_g == k_c:
-                if close(e_g, e_c) and abs(P_g[g, 0] - pl_c[0]) <= DEPTH_REL * pl_c[0]:
-                    ok = True
-                    break
+                if abs(P_g[g, 0] - pl_c[0]) <= DEPTH_REL * pl_c[0]:
+                    if close(e_g, e_c):
+                        ok = True
+                        break
+                    b = bound(pl_c)
+                    if abs(e_g - e_c) <= REL * abs(e_c) + ABS + b:
+                        ok = used_bound = True
+                        break
                 why = "slot %d: energy %.9g vs %.9g, depth %.7g vs %.7g" % (k_g, e_g, e_c, P_g[g, 0], pl_c[0])
                 continue
             hit = np.nonzero(sl_c == k_g)[0]
@@ -133,13 +158,19 @@ def check_refine(orc, ctx, A64, it, B_o=None, E_o=None, K_o=None, M_o=None, samp
                 continue
             e_at = en_c[hit[-1]]
             d_at = pls_c[hit[-1]][0]  # the oracle's plane for the GPU's slot: its depth must match too
-            if e_c - e_at <= MARGIN and close(e_g, e_at) and abs(P_g[g, 0] - d_at) <= DEPTH_REL * d_at:
-                ok = True
-                break
+            if abs(P_g[g, 0] - d_at) <= DEPTH_REL * d_at:
+                if e_c - e_at <= MARGIN and close(e_g, e_at):
+                    ok = True
+                    break
+                b_at, b_c = bound(pls_c[hit[-1]]), bound(pl_c)
+                if e_c - e_at <= MARGIN + b_at + b_c and abs(e_g - e_at) <= REL * abs(e_at) + ABS + b_at:
+                    ok = used_bound = True
+                    break
             why = "slot %d (E %.9g, depth %.7g; oracle there E %.9g, depth %.7g) vs oracle slot %d (E %.9g)" % (
                 k_g, e_g, P_g[g, 0], e_at, d_at, k_c, e_c)
         if ok:
             rep["near_tie_flips"] += 1
+            rep["flip_bound_used"] += used_bound
         else:
             rep["bad"].append((v, s, why + " [final margin %.3g, pivot margin %.3g]" % (m_o, prop_margin)))
     return rep
