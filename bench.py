@@ -59,6 +59,30 @@ def hbm_traffic(kernel):
     return None
 
 
+FUSE_TOL = 0.01   # agreement tolerance of the depth fusion (relative depth)
+
+
+def sweep_evals_per_frame(ctx, w):
+    """Sweep hypotheses decided per frame: levels x non-empty superpixels."""
+    n = sum(int((ctx.get_superpixels(v)[0] > 0).sum()) for v in range(w.rig.n_views))
+    return w.params.levels * n
+
+
+def fusion_record(w, ms):
+    """Depth fusion of all views of the frame: time and algorithmic HBM bytes.
+    Per frame of P pixels over V views: the depth readout (label read and
+    depth write, 8 B/px), pass 1 (depth read, 4 B/px, and the candidate
+    layers written once, 4 (V-1) B/px), pass 2 (layers read once, own depth
+    read, fused and votes written: 4 (V-1) + 12 B/px).  The layer clear
+    (4 (V-1) B/px) is counted apart."""
+    V = w.rig.n_views
+    P = sum(v.W * v.H for v in w.rig.views)
+    algo = P * (8 + 4 + 12) + 2 * 4 * (V - 1) * P
+    return {"ms": ms, "ms_per_view": ms / V, "agree_tol": FUSE_TOL, "algorithmic_hbm_bytes": algo,
+            "clear_bytes": 4 * (V - 1) * P, "achieved_gbs": algo / (ms * 1e-3) / 1e9,
+            "frac_of_8tbs": algo / (ms * 1e-3) / 8e12}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,8 +145,9 @@ def cpu_baseline(w, n_sp):
     A = np.concatenate([random_planes(np.random.default_rng(7 + v), vw.gw, vw.gh, w.params.d_min, w.params.d_max)
                         for v, vw in enumerate(w.rig.views)])
     iters = w.params.iterations
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    cores = max(1, min(cores, 16))
+    host = host_cpus()
+    # one thread per core of the host's CPU share: the GPU machine gives a 1-GPU job 16 cores
+    cores = max(1, min(host["affinity"], 16))
 
     def one(job):
         v, s = job
@@ -138,8 +163,24 @@ def cpu_baseline(w, n_sp):
     dt = time.perf_counter() - t0
     return {"value": evals / dt, "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": "%d superpixels of the full-HD workload: %d-level sweep + %d refinement iterations each "
-                      "(refinement from a seeded plane state); %.1f s wall" % (n_sp, w.params.levels, iters, dt),
-            "seconds": dt}
+                      "(refinement from a seeded plane state); %.1f s wall on %d threads (host: %d CPUs, %d in "
+                      "this process's affinity, %s)" % (n_sp, w.params.levels, iters, dt, cores, host["nproc"],
+                                                       host["affinity"], host["model"]),
+            "host": host, "seconds": dt}
+
+
+def host_cpus():
+    """CPU count of the machine, of this process's affinity mask, and the model name."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"nproc": os.cpu_count() or 1, "affinity": aff, "model": model}
 
 
 def main():
@@ -222,10 +263,18 @@ def main():
     evals, samples, pruned = ctx.work_detail()
     sweep_computed, sweep_total = ctx.sweep_work()
     K = args.steps
+    # depth fusion of the frame's refined depth maps (Sec. III-D), timed on its own
+    ctx.fuse(FUSE_TOL)
+    for _ in range(K):
+        rec("fuse0")
+        ctx.fuse(FUSE_TOL)
+        rec("fuse1")
+    torch.cuda.synchronize()
 
     def span(a, b):
         return [ev[a][k].elapsed_time(ev[b][k]) for k in range(K)]
 
+    t_fuse = span("fuse0", "fuse1")
     t_setup = span("setup0", "sweep0")
     t_sweep = span("sweep0", "sweep1")
     t_ref = [span("ref%d_0" % it, "ref%d_1" % it) for it in range(1, p.iterations + 1)]
@@ -272,6 +321,8 @@ def main():
         "sweep_samples_computed_frac": sweep_computed / max(1, sweep_total),
         "stage_ms": {"setup": float(np.mean(t_setup)), "sweep": sweep_ms, "refine_total": ref_ms,
                      "refine_per_iteration": [float(np.mean(t)) for t in t_ref]},
+        "refine_candidates_scored_in_full_per_s": (evals - pruned - K * sweep_evals_per_frame(ctx, w)) / dt,
+        "fusion": fusion_record(w, float(np.mean(t_fuse))),
         "roofline": {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": peak,
                      "unit": "Tops/s", "frac": achieved / peak, "traffic": hbm_traffic(dom["kernel"]),
                      "traffic_unit": "HBM bytes per launch",
@@ -546,12 +597,11 @@ def run_serving(args):
     latest-frame policy (a rig that frees up takes its newest waiting frame
     and drops older ones), then times one cold solve and one warm frame of
     each rig alone."""
-    import collections
-
     import numpy as np
     import torch
 
     from lfsynth import configs
+    from paper_1812_06856_amd import serve as serving
     from paper_1812_06856_amd import slf
 
     t_gen = time.perf_counter()
@@ -587,77 +637,42 @@ def run_serving(args):
     n_frame = [0] * len(seqs)
     period = 2 * (F - 1)
 
-    def load_frame(j):
+    def next_frame(j):
+        """Index of rig j's next frame: frames 0 .. F-1 .. 1 .. played back and forth."""
         k = n_frame[j]
-        fk = k % period if k % period < F else period - k % period  # frames 0 .. F-1 .. 1 .. played back and forth
-        imgs, labs = data[j][fk]
-        for i, v in enumerate(frames[j][fk].views):
-            ctxs[j].set_image(i, imgs[i])
-            ctxs[j].set_labels(i, labs[i], v.gw, v.gh)
         n_frame[j] += 1
-        return k == 0
-
-    tags = [0]
+        return k % period if k % period < F else period - k % period
 
     def serve(rate, seconds, warmup_s, latest_only, seed):
         rng = np.random.default_rng(seed)
         horizon = warmup_s + seconds
-        arrivals = []
-        t = 0.0
-        while True:
-            t += rng.exponential(1.0 / rate)
-            if t >= horizon:
-                break
-            arrivals.append((t, int(rng.integers(0, len(seqs)))))
-        queue = [collections.deque() for _ in seqs]
-        busy = [None] * len(seqs)  # (arrival, tag) of the rig's request in the pool
-        reading = {}               # tag -> (rig, arrival, event) of depth readouts
-        latency, dropped = [], 0
+        arrivals = serving.poisson_arrivals(rate, horizon, len(seqs), rng)
+        srv = serving.Server(pool, latest_only=latest_only)
+        for j, c in enumerate(ctxs):
+            srv.add_rig(c, streams[j], depth[j], seqs[j].params.iterations, iters_warm)
+            srv.rigs[j].has_state = n_frame[j] > 0
+        latency = []
         a = 0
         samples0 = sum(c.work()[1] for c in ctxs)
         _progress("rate %.0f/s%s: %d arrivals over %.0f s" % (rate, " (latest frame)" if latest_only else "",
                                                             len(arrivals), horizon))
         t0 = time.perf_counter()
+        srv.clock = lambda: time.perf_counter() - t0
         next_report = 5.0
-        while a < len(arrivals) or any(b is not None for b in busy) or reading or any(queue):
-            now = time.perf_counter() - t0
+        while a < len(arrivals) or srv.busy():
+            now = srv.clock()
             while a < len(arrivals) and arrivals[a][0] <= now:
-                queue[arrivals[a][1]].append(arrivals[a][0])
+                t_arr, j = arrivals[a]
+                fk = next_frame(j)
+                srv.submit(j, fk, data[j][fk][0], data[j][fk][1], arrival=t_arr)
                 a += 1
-            for j, c in enumerate(ctxs):
-                if busy[j] is None and queue[j]:
-                    while latest_only and len(queue[j]) > 1:
-                        if queue[j].popleft() >= warmup_s:
-                            dropped += 1
-                    arr = queue[j].popleft()
-                    if load_frame(j):
-                        pool.submit(c, slf.SLF_POOL_SOLVE, 1, seqs[j].params.iterations, tags[0])
-                    else:
-                        c.warm_start()
-                        pool.submit(c, slf.SLF_POOL_PROPAGATE, 1, iters_warm, tags[0])
-                    busy[j] = (arr, tags[0])
-                    tags[0] += 1
-            if pool.usage()["active"]:
-                pool.step()
-            for tg in pool.poll():
-                j = next(i for i, b in enumerate(busy) if b is not None and b[1] == tg)
-                arr = busy[j][0]
-                busy[j] = None
-                for i in range(len(depth[j])):
-                    ctxs[j].get_depth(i, out=depth[j][i])
-                e = torch.cuda.Event()
-                e.record(streams[j])
-                reading[tg] = (j, arr, e)
-            for tg in list(reading):
-                j, arr, e = reading[tg]
-                if e.query():
-                    if arr >= warmup_s:
-                        latency.append((time.perf_counter() - t0 - arr) * 1e3)
-                    del reading[tg]
+            for d in srv.tick():
+                if d.arrival >= warmup_s:
+                    latency.append(d.latency_ms)
             if now >= next_report:
                 _progress("  t=%.0f s: %d arrived, %d measured" % (now, a, len(latency)))
                 next_report += 5.0
-            if not pool.usage()["active"] and not reading:
+            if not pool.usage()["active"]:
                 time.sleep(0.0002)
         wall = time.perf_counter() - t0
         lat = np.array(latency) if latency else np.array([np.nan])
@@ -665,7 +680,7 @@ def run_serving(args):
         return {"rate_fps": rate, "policy": "latest frame" if latest_only else "every frame",
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "max_ms": float(np.max(lat)), "frames_measured": int(len(latency)), "frames_offered": offered,
-                "dropped": dropped, "served_fps": len(latency) / seconds,
+                "dropped": srv.dropped, "served_fps": len(latency) / seconds,
                 "px_view_samples_per_s": (sum(c.work()[1] for c in ctxs) - samples0) / wall, "wall_s": wall}
 
     rates = [float(x) for x in args.serve_rates.split(",")]
@@ -679,6 +694,13 @@ def run_serving(args):
 
     # one cold solve and one warm frame of each rig alone (per-rig calls)
     pool.synchronize()
+    def load_frame(j):
+        fk = next_frame(j)
+        imgs, labs = data[j][fk]
+        for i, v in enumerate(frames[j][fk].views):
+            ctxs[j].set_image(i, imgs[i])
+            ctxs[j].set_labels(i, labs[i], v.gw, v.gh)
+
     solo = []
     for j, c in enumerate(ctxs):
         st = streams[j]
