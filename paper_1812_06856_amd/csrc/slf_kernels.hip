@@ -915,7 +915,7 @@ constexpr int kLdsPix = 1024;  // pixels of a superpixel staged in LDS (the rest
 #define SLF_REFINE_CHAINS 2
 #endif
 constexpr int kChains = SLF_REFINE_CHAINS;  // independent gather chains per lane in the energy loop
-static_assert(kLdsPix % (kChains * kWave) == 0, "the staged pixel list pads to whole passes");
+static_assert(kLdsPix % kWave == 0, "the staged pixel list pads to whole waves");
 
 typedef __attribute__((address_space(3))) uint32_t LdsU32;
 
@@ -1013,7 +1013,7 @@ struct SpCtx {
   float invA;                // 1 / |Omega|
   const LdsU32 *pix_lds;     // pixels 0..n_lds-1 as FP16 pairs (u - ub, v - vb), staged in LDS
   int n_lds;                 // staged pixels (0 if an offset exceeds 2048: FP16 holds integers exactly up to there)
-  int n_pad;                 // n_lds rounded up to whole passes; entries n_lds..n_pad-1 hold a NaN pair
+  int n_pad;                 // n_lds rounded up to whole waves; entries n_lds..n_pad-1 hold a NaN pair
   const LdsRing *ring;       // ring neighbours 0..7
   LdsViewConst *vc;          // constants of up to kViewsPerPass neighbour views
   LdsBest *best;             // plane of the running winner
@@ -1248,14 +1248,16 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         };
         // kChains pixels per lane per pass keep that many gather chains in
         // flight; each lane still accumulates its pixels in order.  The
-        // staged list is padded to whole passes with NaN offsets: a NaN pixel
+        // staged list is padded to whole waves with NaN offsets: a NaN pixel
         // projects to iota = NaN, so it is never seen and adds +0, which
         // leaves the lane's sums unchanged, and its clamped gathers stay in
-        // bounds.  Every pass is then whole, the trip count is uniform, and
-        // the wave-level counts stay in scalar registers.
+        // bounds.  The trip counts are uniform (whole passes, then at most
+        // one wave of pixels on one chain), and the wave-level counts stay in
+        // scalar registers.
         auto samples = [&](auto narrow) {
           const int n_pad = c.n_pad;
-          for (int p0 = 0; p0 < n_pad; p0 += kChains * kWave) {
+          int p0 = 0;
+          for (; p0 + kChains * kWave <= n_pad; p0 += kChains * kWave) {
             Proj q[kChains];
             uint32_t l[kChains];
             float3 C[kChains], G[kChains];
@@ -1270,6 +1272,12 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
             }
 #pragma unroll
             for (int k = 0; k < kChains; ++k) accumulate(q[k], C[k], G[k]);
+          }
+          // the staged list pads to whole waves: a last wave of pixels takes one chain
+          for (; p0 < n_pad; p0 += kWave) {
+            const Proj q = staged(p0 + lane);
+            const uint32_t l = label(q, narrow);
+            accumulate(q, load_f3(tab_rs, (int)(32u * l)), load_f3(tab_rs, (int)(32u * l + 16u)));
           }
           for (int p0 = c.n_lds; p0 < c.A; p0 += kWave) {
             const int p = p0 + lane;
@@ -1415,7 +1423,7 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Wave
   c.vb = (int)floor(cs.y + 0.5);
   bool fits = true;
   const int n_stage = min(c.A, kLdsPix);
-  const int n_pad = (n_stage + kChains * kWave - 1) / (kChains * kWave) * (kChains * kWave);
+  const int n_pad = (n_stage + kWave - 1) / kWave * kWave;
   for (int p = lane; p < n_pad; p += kWave) {
     uint32_t h = 0x7e007e00u;  // FP16 NaN pair: a pixel that is never seen
     if (p < n_stage) {
