@@ -118,6 +118,23 @@ def tiny_custom(W: int, H: int, gw: int, gh: int, *, n_views: int = 3, baseline:
     return Workload(rig.name, rig, MethodParams(levels=levels, iterations=iterations))
 
 
+def sensitivity_rig(sp_px: float = 100.0, seed: int = 21, W: int = 450, H: int = 375, n_views: int = 9,
+                    levels: int = 80) -> Workload:
+    """A Middlebury-like workload for parameter sweeps: 9 rectified views on a
+    line (spacing 0.05, f = 400), 450x375, the tiny scene recipe with 5
+    rectangles (occlusions), superpixels of about sp_px pixels, 80 levels on
+    [2, 8].  The rendering depends on the seed only, so rigs with other
+    superpixel sizes see the same images."""
+    f = 400.0
+    views = rigmod.line_rig(n_views, 0.05, f, W, H)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    scene = make_scene(rng, f=f, W=W, H=H, sp_px=100.0, n_rect=5)
+    gw, gh = grid_for(W, H, sp_px)
+    name = "sens-%dx%dx%d-sp%d" % (n_views, W, H, int(round(sp_px)))
+    rig = build_rig(views, scene, gw, gh, name=name, seed=seed)
+    return Workload(name, rig, MethodParams(levels=levels, d_min=2.0, d_max=8.0, iterations=5))
+
+
 class Sequence:
     """Frames of a static rig filming a moving scene (the serving workload)."""
 
