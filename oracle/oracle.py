@@ -13,7 +13,7 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "slfo.c"), os.path.join(_HERE, "slfo_fuse.c")]
+_SRCS = [os.path.join(_HERE, "slfo.c"), os.path.join(_HERE, "slfo_fuse.c"), os.path.join(_HERE, "slfo_slic.c")]
 _OUT_DIR = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_OUT_DIR, "libslfo.so")
 _lib = None
@@ -83,6 +83,13 @@ def lib():
         L.slfo_refine_trace.argtypes = [P, P, I, I, I, P, P, P, I]
         L.slfo_refine_pivot.argtypes = [P, P, I, I, I, I, P, P, P, P, P, P, I]
         L.slfo_render_depth.argtypes = [P, P, I, P]
+        L.slfo_slic_weight.argtypes = [I, I, I, I, D]
+        L.slfo_slic_weight.restype = ctypes.c_float
+        L.slfo_slic_centres_init.argtypes = [I, I, P, I, I, P]
+        L.slfo_slic_assign.argtypes = [I, I, P, I, I, P, D, P]
+        L.slfo_slic_update.argtypes = [I, I, P, I, I, P, P]
+        L.slfo_slic_connectivity.argtypes = [I, I, I, I, P]
+        L.slfo_slic.argtypes = [I, I, P, I, I, I, D, I, P]
         L.slfo_fuse_project.argtypes = [I, P, P, P, P, P, I, I, P]
         L.slfo_fuse_vote.argtypes = [I, P, ctypes.c_float, P]
         L.slfo_fuse_view.argtypes = [I, P, P, P, P, P, I, ctypes.c_float, P, P, P, P]
@@ -191,6 +198,55 @@ def fuse_vote(cands, tau):
     s = np.empty(len(c), np.int32)
     b = lib().slfo_fuse_vote(len(c), _p(c), ctypes.c_float(tau), _p(s))
     return int(b), s
+
+
+def slic(rgb, gw, gh, iterations=10, compactness=20.0, connectivity=True):
+    """Grid-seeded SLIC labels [H, W] int32 (see oracle/slfo_slic.c)."""
+    rgb = np.ascontiguousarray(rgb, np.uint8)
+    H, W, _ = rgb.shape
+    out = np.empty((H, W), np.int32)
+    rc = lib().slfo_slic(W, H, _p(rgb), gw, gh, iterations, float(compactness), int(bool(connectivity)), _p(out))
+    if rc:
+        raise ValueError("slfo_slic failed: %d" % rc)
+    return out
+
+
+def slic_centres_init(rgb, gw, gh):
+    rgb = np.ascontiguousarray(rgb, np.uint8)
+    H, W, _ = rgb.shape
+    cen = np.empty((gw * gh, 5), np.float32)
+    if lib().slfo_slic_centres_init(W, H, _p(rgb), gw, gh, _p(cen)):
+        raise ValueError("bad arguments")
+    return cen
+
+
+def slic_assign(rgb, gw, gh, cen, compactness=20.0):
+    rgb = np.ascontiguousarray(rgb, np.uint8)
+    H, W, _ = rgb.shape
+    cen = np.ascontiguousarray(cen, np.float32)
+    out = np.empty((H, W), np.int32)
+    if lib().slfo_slic_assign(W, H, _p(rgb), gw, gh, _p(cen), float(compactness), _p(out)):
+        raise ValueError("bad arguments")
+    return out
+
+
+def slic_update(rgb, gw, gh, labels, cen):
+    rgb = np.ascontiguousarray(rgb, np.uint8)
+    H, W, _ = rgb.shape
+    labels = np.ascontiguousarray(labels, np.int32)
+    cen = np.array(cen, np.float32, copy=True)
+    rc = lib().slfo_slic_update(W, H, _p(rgb), gw, gh, _p(labels), _p(cen))
+    if rc:
+        raise ValueError("slfo_slic_update failed: %d" % rc)
+    return cen
+
+
+def slic_connectivity(labels, gw, gh):
+    lab = np.array(labels, np.int32, copy=True)
+    H, W = lab.shape
+    if lib().slfo_slic_connectivity(W, H, gw, gh, _p(lab)):
+        raise ValueError("slfo_slic_connectivity failed")
+    return lab
 
 
 class Oracle:

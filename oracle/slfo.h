@@ -138,6 +138,21 @@ int slfo_fuse_view(int n_views, const int32_t *wh, const double *K, const double
                    const float *depth, int ref, float tau, float *fused, int32_t *winner, int32_t *stability,
                    int32_t *n_cand);
 
+/* Grid-seeded SLIC segmentation (Sec. III-A; its GPU form, Sec. III-E); the
+ * definition is in slfo_slic.c.  rgb H x W x 3; labels H x W; centres [gw gh][5]
+ * = (u, v, r, g, b) in FP32.  slfo_slic: `iterations` assignment passes with a
+ * centre update between consecutive ones, then (connectivity != 0) the
+ * connectivity step.  Returns 0, -1 bad arguments, -2 a label out of range,
+ * -3 out of memory. */
+float slfo_slic_weight(int W, int H, int gw, int gh, double compactness);
+int slfo_slic_centres_init(int W, int H, const uint8_t *rgb, int gw, int gh, float *cen);
+int slfo_slic_assign(int W, int H, const uint8_t *rgb, int gw, int gh, const float *cen, double compactness,
+                     int32_t *labels);
+int slfo_slic_update(int W, int H, const uint8_t *rgb, int gw, int gh, const int32_t *labels, float *cen);
+int slfo_slic_connectivity(int W, int H, int gw, int gh, int32_t *labels);
+int slfo_slic(int W, int H, const uint8_t *rgb, int gw, int gh, int iterations, double compactness,
+              int connectivity, int32_t *labels);
+
 #ifdef __cplusplus
 }
 #endif
