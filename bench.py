@@ -60,6 +60,7 @@ def hbm_traffic(kernel):
 
 
 FUSE_TOL = 0.01   # agreement tolerance of the depth fusion (relative depth)
+SLIC_ITERATIONS, SLIC_COMPACTNESS = 10, 20.0   # the GPU segmentation timed beside the step
 
 
 def sweep_evals_per_frame(ctx, w):
@@ -267,6 +268,7 @@ def main():
     evals, samples, pruned = ctx.work_detail()
     sweep_computed, sweep_total = ctx.sweep_work()
     K = args.steps
+    sweep_evals_frame = sweep_evals_per_frame(ctx, w)
     # depth fusion of the frame's refined depth maps (Sec. III-D), timed on its own
     ctx.fuse(FUSE_TOL)
     for _ in range(K):
@@ -278,6 +280,14 @@ def main():
     def span(a, b):
         return [ev[a][k].elapsed_time(ev[b][k]) for k in range(K)]
 
+    # GPU SLIC of every view of the frame (Sec. III-A; the step before the hot path), timed on its own
+    for _ in range(K):
+        rec("seg0")
+        for i in range(V):
+            ctx.segment(i, vs[i].gw, vs[i].gh, SLIC_ITERATIONS, SLIC_COMPACTNESS)
+        rec("seg1")
+    torch.cuda.synchronize()
+    t_seg = span("seg0", "seg1")
     t_fuse = span("fuse0", "fuse1")
     t_setup = span("setup0", "sweep0")
     t_sweep = span("sweep0", "sweep1")
@@ -325,8 +335,10 @@ def main():
         "sweep_samples_computed_frac": sweep_computed / max(1, sweep_total),
         "stage_ms": {"setup": float(np.mean(t_setup)), "sweep": sweep_ms, "refine_total": ref_ms,
                      "refine_per_iteration": [float(np.mean(t)) for t in t_ref]},
-        "refine_candidates_scored_in_full_per_s": (evals - pruned - K * sweep_evals_per_frame(ctx, w)) / dt,
+        "refine_candidates_scored_in_full_per_s": (evals - pruned - K * sweep_evals_frame) / dt,
         "fusion": fusion_record(w, float(np.mean(t_fuse))),
+        "segmentation": {"ms": float(np.mean(t_seg)), "ms_per_view": float(np.mean(t_seg)) / V,
+                         "iterations": SLIC_ITERATIONS, "compactness": SLIC_COMPACTNESS, "grid": [vs[0].gw, vs[0].gh]},
         "roofline": {"bound": "alu", "kernel": dom["kernel"], "achieved": achieved, "peak": peak,
                      "unit": "Tops/s", "frac": achieved / peak, "traffic": hbm_traffic(dom["kernel"]),
                      "traffic_unit": "HBM bytes per launch",

@@ -127,6 +127,31 @@ int slf_set_image_rgb8(slf_ctx *ctx, int view, const uint8_t *rgb, int64_t row_s
 int slf_set_labels(slf_ctx *ctx, int view, const int32_t *labels, int64_t row_stride_elems, int grid_w,
                    int grid_h, int is_device);
 
+/* Segments the view's image (set with slf_set_image_rgb8) on the GPU into
+ * grid_w x grid_h SLIC superpixels and makes them the view's labels, as
+ * slf_set_labels would (Sec. III-A: SLIC superpixels read as a regular grid of
+ * cells; Sec. III-E: the segmentation runs on the GPU).  Cluster k = gy gw +
+ * gx starts at the centre of grid cell (gx, gy) with the colour of the nearest
+ * pixel; each of `iterations` passes assigns every pixel to the closest centre
+ * of the 3 x 3 cells around its own, D = |rgb - rgb_k|^2 + ((u - u_k)^2 + (v
+ * - v_k)^2) (2.55 compactness)^2 gw gh / (W H) with colours in 0..255 (ties:
+ * the first centre in row-major order of the 3 x 3 cells), and moves each
+ * centre to the mean position and colour of its pixels between passes.  Then
+ * each label keeps only its largest 4-connected component (equal sizes: the
+ * one whose first pixel in raster order comes first); every other component
+ * takes the final label of the component holding the pixel left of its first
+ * pixel, or above it in the first column (the component holding pixel (0,0)
+ * keeps its label).  Results are deterministic.  SLF_ESTATE without an image;
+ * SLF_EINVAL unless 1 <= grid_w <= W, 1 <= grid_h <= H, grid_w grid_h <=
+ * 2^24, iterations >= 1 and compactness finite and >= 0.  Allocates its
+ * working buffers (12 bytes per pixel, 28 per cluster) on first use.
+ * Asynchronous. */
+int slf_segment(slf_ctx *ctx, int view, int grid_w, int grid_h, int iterations, float compactness);
+/* Copies a view's labels (set or segmented): H rows separated by
+ * row_stride_elems (>= W).  is_device = 0: host buffer, synchronises; 1:
+ * device buffer, asynchronous.  SLF_ESTATE if the view has no labels. */
+int slf_get_labels(slf_ctx *ctx, int view, int32_t *out, int64_t row_stride_elems, int is_device);
+
 /* Builds the device image texels and the superpixel pixel lists and
  * statistics (Sec. III-A, III-C-1: area, centroid, mean colour) for the
  * current images and labels.  slf_sweep, slf_set_planes and slf_propagate do

@@ -10,9 +10,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libslf.so")
-SOURCES = ["slf_api.hip", "slf_kernels.hip", "slf_pool.hip", "slf_fusion.hip"]
-# the fusion's FP64 projection is one fixed sequence of correctly rounded operations
-EXTRA_FLAGS = {"slf_fusion.hip": ["-ffp-contract=off"]}
+SOURCES = ["slf_api.hip", "slf_kernels.hip", "slf_pool.hip", "slf_fusion.hip", "slf_slic.hip"]
+# the fusion's FP64 projection and the segmentation's FP32 distances are fixed
+# sequences of correctly rounded operations
+EXTRA_FLAGS = {"slf_fusion.hip": ["-ffp-contract=off"], "slf_slic.hip": ["-ffp-contract=off"]}
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -125,7 +125,10 @@ void free_all(slf_ctx *c) {
   dfree(c->d_work);
   dfree(c->d_claims);
   dfree(c->d_depth_tmp);
-  for (void **f : {&c->d_fz, &c->d_fcams, &c->d_fdepth, &c->d_fused, &c->d_fvotes}) dfree(*f);
+  for (void **f : {&c->d_fz, &c->d_fcams, &c->d_fdepth, &c->d_fused, &c->d_fvotes, &c->d_slic_cen, &c->d_slic_best,
+                   &c->d_slic_work})
+    dfree(*f);
+  c->slic_cen_bytes = c->slic_best_bytes = c->slic_work_bytes = 0;
   c->fz_bytes = c->fcams_bytes = c->fdepth_bytes = c->fused_bytes = c->fvotes_bytes = 0;
   c->fcams_h.clear();
   c->has_fused = false;

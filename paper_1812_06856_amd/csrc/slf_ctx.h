@@ -85,6 +85,10 @@ struct slf_ctx {
   int64_t fz_bytes = 0, fcams_bytes = 0, fdepth_bytes = 0, fused_bytes = 0, fvotes_bytes = 0;
   std::vector<unsigned char> fcams_h;
   bool has_fused = false;
+  // GPU SLIC (slf_slic.hip), allocated on first use: centres, per-label best
+  // component, and per-pixel working labels, union-find parents and sizes
+  void *d_slic_cen = nullptr, *d_slic_best = nullptr, *d_slic_work = nullptr;
+  int64_t slic_cen_bytes = 0, slic_best_bytes = 0, slic_work_bytes = 0;
   int cur = 0;
   std::vector<int> area_h;
   std::vector<double2> cen_h;

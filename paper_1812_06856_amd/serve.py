@@ -5,7 +5,8 @@ on the device; frames are admitted into the pool's stages as rigs free up
 at the next stage boundary); latency runs from arrival to the frame's depth
 maps in device memory.
 
-A rig's first frame is solved in full (the sweep, Sec. III-B, then
+Frames come with label maps or are segmented on the GPU when admitted
+(slf_segment, Sec. III-A / III-E).  A rig's first frame is solved in full (the sweep, Sec. III-B, then
 `cold_iters` refinement iterations, Sec. III-C); later frames start from the
 rig's previous planes (slf_warm_start: each grid cell keeps its 3D plane and
 takes the depth at its new centroid; the paper treats frames independently,
@@ -65,8 +66,11 @@ class Server:
     agreement tolerance (written to the rig's `fused` buffers)."""
 
     def __init__(self, pool: "slf.Pool", latest_only: bool = False, fuse_tol: Optional[float] = None,
-                 clock: Callable[[], float] = time.perf_counter):
+                 clock: Callable[[], float] = time.perf_counter, segment: Optional[tuple] = None):
+        """segment: (iterations, compactness) of the GPU SLIC for frames
+        submitted without labels (the rig's label grid is kept)."""
         self.pool = pool
+        self.segment = segment
         self.latest_only = latest_only
         self.fuse_tol = fuse_tol
         self.clock = clock
@@ -84,10 +88,14 @@ class Server:
         self.rigs.append(_Rig(ctx, stream, depth, cold_iters, warm_iters, fused))
         return len(self.rigs) - 1
 
-    def submit(self, rig: int, frame, images: Sequence[torch.Tensor], labels: Sequence[torch.Tensor],
+    def submit(self, rig: int, frame, images: Sequence[torch.Tensor], labels: Optional[Sequence[torch.Tensor]],
                arrival: Optional[float] = None) -> None:
         """Queues a frame of `rig`: device uint8 images [H, W, 3] and int32 label
-        maps [H, W] per view (kept alive by the caller until served)."""
+        maps [H, W] per view (kept alive by the caller until served).  With
+        labels None the frame is segmented on the GPU (slf_segment, with the
+        server's `segment` settings) when it is admitted."""
+        if labels is None and self.segment is None:
+            raise ValueError("no labels and no GPU segmentation configured")
         self.rigs[rig].queue.append((frame, self.clock() if arrival is None else arrival, images, labels))
 
     def busy(self) -> bool:
@@ -98,10 +106,13 @@ class Server:
             r.queue.popleft()
             self.dropped += 1
         frame, arrival, images, labels = r.queue.popleft()
-        for v, (img, lab) in enumerate(zip(images, labels)):
+        for v, img in enumerate(images):
             gw, gh = r.ctx.grids[v]
             r.ctx.set_image(v, img)
-            r.ctx.set_labels(v, lab, gw, gh)
+            if labels is None:
+                r.ctx.segment(v, gw, gh, *self.segment)
+            else:
+                r.ctx.set_labels(v, labels[v], gw, gh)
         cold = not r.has_state
         if cold:
             self.pool.submit(r.ctx, slf.SLF_POOL_SOLVE, 1, r.cold_iters, self._tag)

@@ -25,7 +25,7 @@ EXPORTED = [
     "slf_set_neighbors", "slf_set_image_rgb8", "slf_set_labels", "slf_prepare", "slf_sweep", "slf_set_planes", "slf_propagate",
     "slf_get_planes", "slf_get_depth", "slf_get_superpixels", "slf_get_work", "slf_get_sweep_work", "slf_reset_work", "slf_synchronize",
     "slf_status_string", "slf_last_error", "slf_warm_start", "slf_get_footprint",
-    "slf_fuse", "slf_get_fused_depth", "slf_fuse_depth", "slf_fuse_depth_static",
+    "slf_fuse", "slf_get_fused_depth", "slf_fuse_depth", "slf_fuse_depth_static", "slf_segment", "slf_get_labels",
     "slf_pool_default_config", "slf_pool_create", "slf_pool_destroy", "slf_pool_set_stream", "slf_pool_set_config",
     "slf_pool_get_config", "slf_pool_attach", "slf_pool_detach", "slf_pool_usage", "slf_pool_submit", "slf_pool_step",
     "slf_pool_run", "slf_pool_poll", "slf_pool_synchronize", "slf_pool_autotune", "slf_pool_last_error",
@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
     L.slf_warm_start.argtypes = [P]
     L.slf_get_footprint.argtypes = [P, PU64]
     L.slf_fuse.argtypes = [P, ctypes.c_float]
+    L.slf_segment.argtypes = [P, I, I, I, I, ctypes.c_float]
+    L.slf_get_labels.argtypes = [P, I, P, I64, I]
     L.slf_get_fused_depth.argtypes = [P, I, P, I64, P, I]
     L.slf_fuse_depth.argtypes = [P, P, P, P, ctypes.c_float]
     L.slf_fuse_depth_static.argtypes = [P, P, P, P, ctypes.c_float]
@@ -236,6 +238,21 @@ class Context:
             a = np.ascontiguousarray(labels, np.int32)
             self._check(self._L.slf_set_labels(self._h, view, _ptr(a), a.shape[1], grid_w, grid_h, 0))
         self.grids[view] = (grid_w, grid_h)
+
+    def segment(self, view: int, grid_w: int, grid_h: int, iterations: int = 10, compactness: float = 20.0) -> None:
+        """GPU SLIC of the view's image into the view's labels (slf_segment)."""
+        self._check(self._L.slf_segment(self._h, view, grid_w, grid_h, iterations, float(compactness)))
+        self.grids[view] = (grid_w, grid_h)
+
+    def get_labels(self, view: int, out: Optional[torch.Tensor] = None):
+        W, H = self.dims[view]
+        if out is not None:
+            assert out.is_cuda and out.dtype == torch.int32 and out.stride(1) == 1
+            self._check(self._L.slf_get_labels(self._h, view, _ptr(out), out.stride(0), 1))
+            return out
+        a = np.empty((H, W), np.int32)
+        self._check(self._L.slf_get_labels(self._h, view, _ptr(a), W, 0))
+        return a
 
     def load_rig(self, rig, params=None) -> None:
         """Cameras, neighbour lists, images and labels of an input rig (host arrays)."""

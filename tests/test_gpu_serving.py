@@ -205,3 +205,36 @@ def test_served_frames_with_fusion():
     c.close()
     alone.close()
     pool.close()
+
+
+def test_served_frames_segmented_on_the_gpu():
+    """Frames submitted without labels are segmented on the GPU when admitted:
+    the served result equals the same frame served with the oracle's SLIC
+    labels (the segmentation's own parity is tested against the oracle)."""
+    import torch
+    from oracle import oracle
+    from paper_1812_06856_amd import serve, slf
+
+    s = configs.tiny_sequence(seed=65)
+    f0 = s.frame(0)
+    out = []
+    for gpu_slic in (True, False):
+        pool = slf.Pool(0)
+        srv = serve.Server(pool, segment=(10, 20.0))
+        c = _ctx(f0, s.params)
+        st = torch.cuda.Stream()
+        c.set_stream(st)
+        pool.attach(c)
+        depth = [torch.empty((v.H, v.W), dtype=torch.float32, device="cuda") for v in f0.views]
+        srv.add_rig(c, st, depth, s.params.iterations, 2)
+        imgs = [torch.from_numpy(v.rgb).cuda() for v in f0.views]
+        labs = None if gpu_slic else [torch.from_numpy(oracle.slic(v.rgb, v.gw, v.gh, 10, 20.0)).cuda()
+                                      for v in f0.views]
+        srv.submit(0, 0, imgs, labs)
+        assert len(srv.drain()) == 1
+        out.append([d.cpu().numpy() for d in depth])
+        pool.detach(c)
+        c.close()
+        pool.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
