@@ -122,6 +122,14 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// floor(x + 0.5) as an integer, the sum taken exactly (v_cvt_rpi_i32_f32; a
+// NaN gives 0).  The compiler does not form this instruction by itself.
+__device__ __forceinline__ int round_half_up(float x) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 // Lane `l`'s value, uniform over the wave (l must be wave-uniform).
 __device__ __forceinline__ float bcast(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
@@ -1165,11 +1173,10 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         const float cax = q.ax, caxu = uni_f(q.axu), caxv = uni_f(q.axv);
         const float cay = q.ay, cayu = uni_f(q.ayu), cayv = uni_f(q.ayv);
         const float caw = q.aw, cawu = uni_f(q.awu), cawv = uni_f(q.awv);
-        const float fX0 = (float)__builtin_amdgcn_readfirstlane(q.X0);
-        const float fY0 = (float)__builtin_amdgcn_readfirstlane(q.Y0);
+        const int iX0 = __builtin_amdgcn_readfirstlane(q.X0), iY0 = __builtin_amdgcn_readfirstlane(q.Y0);
+        const float fX0 = (float)iX0, fY0 = (float)iY0;
         const ViewDev &vi = ro_at(a.views, ro_at(a.pairs, vw.pair_off + base + jv).i);
-        const float Wm1 = (float)(vi.W - 1), Hm1 = (float)(vi.H - 1);
-        const uint32_t Wv = (uint32_t)vi.W;
+        const uint32_t Wv = (uint32_t)vi.W, Hv = (uint32_t)vi.H;
         // 16-bit labels when every view has at most 65536 cells: half the
         // bytes of the label windows the gathers touch.
         const uint32_t npx = (uint32_t)vi.W * (uint32_t)vi.H;
@@ -1203,12 +1210,14 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           const float rw = rcp(q.w);
           q.dx = fmaf(caxu, du, fmaf(caxv, dv, cax)) * rw;
           q.dy = fmaf(cayu, du, fmaf(cayv, dv, cay)) * rw;
-          const float uf = fX0 + floorf(q.dx + 0.5f), vf = fY0 + floorf(q.dy + 0.5f);
-          // clamp into the image (a NaN fails the equality and converts to 0)
-          const float uc = __builtin_amdgcn_fmed3f(uf, 0.f, Wm1), vc = __builtin_amdgcn_fmed3f(vf, 0.f, Hm1);
+          // nearest pixel (round half up, in one instruction and without
+          // rounding x + 0.5 first); inside the image iff 0 <= u < W, 0 <= v < H
+          const int ui = iX0 + round_half_up(q.dx), vi = iY0 + round_half_up(q.dy);
           q.seen = __builtin_amdgcn_ballot_w64(q.iota > 0.f) & __builtin_amdgcn_ballot_w64(q.w > 0.f) &
-                   __builtin_amdgcn_ballot_w64(uc == uf) & __builtin_amdgcn_ballot_w64(vc == vf);
-          q.pix = __umul24((uint32_t)(int)vc, Wv) + (uint32_t)(int)uc;  // sides below 2^16
+                   __builtin_amdgcn_ballot_w64((uint32_t)ui < Wv) & __builtin_amdgcn_ballot_w64((uint32_t)vi < Hv);
+          // outside the image (not seen) the offset is arbitrary: the gathers
+          // are bounded by their buffer resources and the sample is masked out
+          q.pix = __umul24((uint32_t)vi, Wv) + (uint32_t)ui;  // sides below 2^16
           return q;
         };
         auto label = [&](const Proj &q, auto narrow) -> uint32_t {
