@@ -79,6 +79,20 @@ __device__ __forceinline__ float wave_sum(float x) {
   x += dpp_f<kDppMirror>(x);
   return (rd_f(x, 0) + rd_f(x, 16)) + (rd_f(x, 32) + rd_f(x, 48));
 }
+// Sums of two values over the wave at once: v_permlane32_swap exchanges the
+// upper half of a with the lower half of b, so one add leaves the 32-lane
+// partial sums of a in lanes 0..31 and of b in lanes 32..63; the row steps
+// then reduce both together.  Fixed order; the whole wave must be active.
+__device__ __forceinline__ void wave_sum2(float a, float b, float &sa, float &sb) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  float x = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  x += dpp_f<kDppXor1>(x);
+  x += dpp_f<kDppXor2>(x);
+  x += dpp_f<kDppHalfMirror>(x);
+  x += dpp_f<kDppMirror>(x);
+  sa = rd_f(x, 0) + rd_f(x, 16);
+  sb = rd_f(x, 32) + rd_f(x, 48);
+}
 __device__ __forceinline__ int wave_sum_i(int x) {
   x += dpp_i<kDppXor1>(x);
   x += dpp_i<kDppXor2>(x);
@@ -1297,8 +1311,8 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           samples(std::true_type{});
         else
           samples(std::false_type{});
-        const float swt = wave_sum(sw);
-        const float gxt = wave_sum(gx);
+        float swt, gxt;
+        wave_sum2(sw, gx, swt, gxt);
         const int nXt = nX;
         const bool Y = occluded != 0ull;
         const float Si = swt * c.invA;
