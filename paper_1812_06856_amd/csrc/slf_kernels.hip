@@ -136,6 +136,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// 1 / x in FP64 from the hardware reciprocal and one Newton step (a few ulp;
+// the plane geometry it serves is rounded to FP32 before any sample uses it).
+__device__ __forceinline__ double rcp_d(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // floor(x + 0.5) as an integer, the sum taken exactly (v_cvt_rpi_i32_f32; a
 // NaN gives 0).  The compiler does not form this instruction by itself.
 __device__ __forceinline__ int round_half_up(float x) {
@@ -1109,14 +1116,14 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         const double t = nx * r.rx + ny * r.ry + nz * r.rz;
         float sj = 0.f;
         if (t > 0.0) {
-          const float dd = (float)(r.d - delta / t);
+          const float dd = (float)(r.d - delta * rcp_d(t));
           sj = __expf(-dd * dd * a.inv2sig2);
         }
         num = r.w * sj;
         den = r.w;
       }
     }
-    Es = ring_sum(num) / ring_sum(den);
+    Es = ring_sum(num) * rcp(ring_sum(den));  // the nearest colour has weight 1, so den >= 1
   }
 
   const float occ = (a.term_mask & 4u) ? a.eta * (1.f - c.omega_min) : 0.f;
@@ -1135,7 +1142,7 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
   // into LDS) and read back into scalar registers view by view.
   float Ec = 1.f;
   if (a.term_mask & 2u) {
-    const double idl = 1.0 / delta;
+    const double idl = rcp_d(delta);
     const double gd0 = (nx * vw.Kinv_d[0] + ny * vw.Kinv_d[3] + nz * vw.Kinv_d[6]) * idl;
     const double gd1 = (nx * vw.Kinv_d[1] + ny * vw.Kinv_d[4] + nz * vw.Kinv_d[7]) * idl;
     const double gd2 = (nx * vw.Kinv_d[2] + ny * vw.Kinv_d[5] + nz * vw.Kinv_d[8]) * idl;
@@ -1159,7 +1166,9 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         const double hy = H[3] * c.ub + H[4] * c.vb + H[5];
         const double hw = H[6] * c.ub + H[7] * c.vb + H[8];
         if (hw > 0.0) {
-          const double xc = hx / hw, yc = hy / hw;
+          // only the re-centring pixel: any nearby integer serves, so FP32 suffices
+          const float rhw = rcp((float)hw);
+          const double xc = (double)((float)hx * rhw), yc = (double)((float)hy * rhw);
           if (fabs(xc) < 1.0e7 && fabs(yc) < 1.0e7) {
             X0 = (int)floor(xc + 0.5);
             Y0 = (int)floor(yc + 0.5);
@@ -1394,7 +1403,7 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
       c.best->ny = cd.ny;
       c.best->nz = cd.nz;
       c.best->delta = cd.delta;
-      c.best->d = cd.delta / (cd.nx * c.rsx + cd.ny * c.rsy + cd.nz * c.rsz);  // depth at the centroid
+      c.best->d = cd.delta * rcp_d(cd.nx * c.rsx + cd.ny * c.rsy + cd.nz * c.rsz);  // depth at the centroid
     } else if (E > b.second) {
       b.second = E;
     }
