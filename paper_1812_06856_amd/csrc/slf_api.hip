@@ -124,6 +124,7 @@ void free_all(slf_ctx *c) {
   dfree(c->d_err);
   dfree(c->d_work);
   dfree(c->d_claims);
+  dfree(c->d_refine_args);
   dfree(c->d_depth_tmp);
   for (void **f : {&c->d_fz, &c->d_fcams, &c->d_fdepth, &c->d_fused, &c->d_fvotes, &c->d_slic_cen, &c->d_slic_best,
                    &c->d_slic_work})
@@ -491,7 +492,8 @@ int slf_create(int device_ordinal, slf_ctx **out) {
   if (hipMalloc((void **)&c->d_err, sizeof(int)) != hipSuccess ||
       hipMalloc((void **)&c->d_work, kWorkCounters * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->d_work, 0, kWorkCounters * sizeof(unsigned long long)) != hipSuccess ||
-      hipMalloc((void **)&c->d_claims, kPoolQueues * kPoolCounterStride * sizeof(int)) != hipSuccess) {
+      hipMalloc((void **)&c->d_claims, kPoolQueues * kPoolCounterStride * sizeof(int)) != hipSuccess ||
+      hipMalloc((void **)&c->d_refine_args, sizeof(RefineArgs)) != hipSuccess) {
     free_all(c);
     delete c;
     return SLF_ENOMEM;
@@ -519,6 +521,9 @@ int slf_destroy(slf_ctx *c) {
 int slf_set_stream(slf_ctx *c, void *stream) {
   if (!c) return SLF_EINVAL;
   if (int rc = check_idle(c)) return rc;
+  // the refinement's argument slot is rewritten on the new stream: let the old one finish with it
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   c->stream = (hipStream_t)stream;
   return SLF_OK;
 }
@@ -746,7 +751,7 @@ int slf_propagate(slf_ctx *c, int first_iter, int n_iters) {
   for (int it = first_iter; it < first_iter + n_iters; ++it) {
     RefineArgs a;
     refine_args(c, it, a);
-    HIP_OR_FAIL(c, launch_refine(c->p.image_precision, a, c->stream));
+    HIP_OR_FAIL(c, launch_refine(c->p.image_precision, a, c->d_refine_args, c->stream));
     after_refine(c);
   }
   return SLF_OK;

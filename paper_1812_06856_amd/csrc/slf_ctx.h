@@ -75,6 +75,7 @@ struct slf_ctx {
   // [2] refinement candidates pruned, [3] sweep samples computed
   unsigned long long *d_work = nullptr;
   int *d_claims = nullptr;  // claim counters of the persistent sweep launch
+  slf::RefineArgs *d_refine_args = nullptr;  // refinement launch arguments, written on the stream before each launch
   int n_cu = 0;             // compute units of the device
   float *d_depth_tmp = nullptr;
   int64_t depth_tmp_n = 0;
