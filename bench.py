@@ -269,6 +269,7 @@ def main():
     sweep_computed, sweep_total = ctx.sweep_work()
     K = args.steps
     sweep_evals_frame = sweep_evals_per_frame(ctx, w)
+    sweep_scored, sweep_decided = ctx.sweep_levels()
     # depth fusion of the frame's refined depth maps (Sec. III-D), timed on its own
     ctx.fuse(FUSE_TOL)
     for _ in range(K):
@@ -336,6 +337,8 @@ def main():
         "stage_ms": {"setup": float(np.mean(t_setup)), "sweep": sweep_ms, "refine_total": ref_ms,
                      "refine_per_iteration": [float(np.mean(t)) for t in t_ref]},
         "refine_candidates_scored_in_full_per_s": (evals - pruned - K * sweep_evals_frame) / dt,
+        "hypotheses_scored_in_full_per_s": (sweep_scored + evals - pruned - sweep_decided) / dt,
+        "sweep_levels_scored_frac": sweep_scored / max(1, sweep_decided),
         "fusion": fusion_record(w, float(np.mean(t_fuse))),
         "segmentation": {"ms": float(np.mean(t_seg)), "ms_per_view": float(np.mean(t_seg)) / V,
                          "iterations": SLIC_ITERATIONS, "compactness": SLIC_COMPACTNESS, "grid": [vs[0].gw, vs[0].gh]},

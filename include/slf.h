@@ -232,6 +232,12 @@ int slf_get_work(slf_ctx *ctx, uint64_t *evals, uint64_t *samples, uint64_t *pru
  * orders the chunks included); total: the samples of a sweep without that
  * bound (pixels x neighbour views x levels).  Synchronises. */
 int slf_get_sweep_work(slf_ctx *ctx, uint64_t *computed, uint64_t *total);
+/* Sweep levels since the last reset (Sec. III-B): scored, those whose cost
+ * (eq. 2) was summed over every pixel and neighbour view, i.e. not stopped by
+ * the level bound of slf_get_sweep_work; decided, every level of every
+ * non-empty superpixel (the sweep's share of slf_get_work's evals).  Either
+ * output may be NULL.  Synchronises. */
+int slf_get_sweep_levels(slf_ctx *ctx, uint64_t *scored, uint64_t *decided);
 int slf_reset_work(slf_ctx *ctx);
 /* Waits for all work enqueued by the context. */
 int slf_synchronize(slf_ctx *ctx);

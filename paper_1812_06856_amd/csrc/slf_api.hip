@@ -856,7 +856,7 @@ int slf_get_work(slf_ctx *c, uint64_t *evals, uint64_t *samples, uint64_t *prune
   if (!c) return SLF_EINVAL;
   if (int rc = check_idle(c)) return rc;
   HIP_OR_FAIL(c, hipSetDevice(c->device));
-  unsigned long long w[kWorkCounters] = {0, 0, 0, 0};
+  unsigned long long w[kWorkCounters] = {};
   HIP_OR_FAIL(c, hipMemcpyAsync(w, c->d_work, sizeof w, hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   if (evals) *evals = c->host_evals + w[0];
@@ -874,6 +874,18 @@ int slf_get_sweep_work(slf_ctx *c, uint64_t *computed, uint64_t *total) {
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   if (computed) *computed = w;
   if (total) *total = c->host_sweep_total;
+  return SLF_OK;
+}
+
+int slf_get_sweep_levels(slf_ctx *c, uint64_t *scored, uint64_t *decided) {
+  if (!c) return SLF_EINVAL;
+  if (int rc = check_idle(c)) return rc;
+  HIP_OR_FAIL(c, hipSetDevice(c->device));
+  unsigned long long w = 0;
+  HIP_OR_FAIL(c, hipMemcpyAsync(&w, c->d_work + 4, sizeof w, hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (scored) *scored = w;
+  if (decided) *decided = c->host_evals;
   return SLF_OK;
 }
 

@@ -72,7 +72,8 @@ struct slf_ctx {
   float *d_energy = nullptr, *d_margin = nullptr;
   int *d_choice = nullptr;
   // device work counters: [0] refinement evals, [1] refinement samples,
-  // [2] refinement candidates pruned, [3] sweep samples computed
+  // [2] refinement candidates pruned, [3] sweep samples computed, [4] sweep
+  // levels scored over all pixels and views
   unsigned long long *d_work = nullptr;
   int *d_claims = nullptr;  // claim counters of the persistent sweep launch
   slf::RefineArgs *d_refine_args = nullptr;  // refinement launch arguments, written on the stream before each launch

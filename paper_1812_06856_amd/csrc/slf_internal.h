@@ -68,7 +68,8 @@ struct SweepArgs {
   float *cost;         // out
   int *choice;         // out
   float *margin;       // out
-  unsigned long long *work;  // [3] += px-view samples computed (the level bound skips the rest)
+  unsigned long long *work;  // [3] += px-view samples computed (the level bound skips the rest),
+                             // [4] += levels scored over all pixels and views
 };
 
 struct RefineArgs {
@@ -116,7 +117,7 @@ struct PoolJob {
 };
 constexpr int kPoolQueues = 8;      // one per XCD
 constexpr int kPoolMaxJobs = 64;    // rigs in one stage
-constexpr int kWorkCounters = 4;      // per-context device work counters (slf_ctx::d_work)
+constexpr int kWorkCounters = 5;      // per-context device work counters (slf_ctx::d_work)
 constexpr int kPoolCounterStride = 16;  // ints between claim counters (one 64-byte line each)
 // A stage: every job runs the same op in the same image format.  Items
 // [qbegin[q], qend[q]) form queue q; the waves of XCD q drain it first.

@@ -690,7 +690,8 @@ __device__ __forceinline__ bool coarse_order(const SweepArgs &a, const int g, co
 template <int FMT, int KC>
 __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, const int v, const int s,
                                              const ViewDev &vw, const int A, const int k_begin, const int k_end,
-                                             float &best, float &second, int &kbest, uint64_t &computed) {
+                                             float &best, float &second, int &kbest, uint64_t &computed,
+                                             uint32_t &scored) {
   const int lane = threadIdx.x & (kWave - 1);
   const int N = vw.n_pairs;
   const int P = A * N;
@@ -802,6 +803,7 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
     }
     computed += (uint64_t)min(P, passes * kWave) * (uint64_t)min(KC, k_end - k0);
     if (passes < n_pass) continue;  // no level of this chunk can be the best (or, with exact_margin, the second best)
+    scored += (uint32_t)min(KC, k_end - k0);
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk) {
       const float C = wave_sum(acc[kk]);
@@ -856,10 +858,12 @@ __device__ __forceinline__ void sweep_sp(const SweepArgs &a, const int g) {
   float best = INFINITY, second = INFINITY;
   int kbest = 0;
   uint64_t computed = 0;
-  sweep_levels<FMT, KC>(a, g, v, s, vw, A, 0, a.levels, best, second, kbest, computed);
+  uint32_t scored = 0;
+  sweep_levels<FMT, KC>(a, g, v, s, vw, A, 0, a.levels, best, second, kbest, computed, scored);
   if (lane == 0) {
     sweep_finish(a, g, v, s, A, vw.n_pairs, best, second, kbest);
     atomicAdd(&a.work[3], (unsigned long long)computed);
+    atomicAdd(&a.work[4], (unsigned long long)scored);
   }
 }
 
@@ -884,10 +888,12 @@ __device__ __forceinline__ void sweep_part(const SweepArgs &a, const int g, cons
   int kbest = 0;
   uint64_t computed = 0;  // the bound references this part's own complete levels (best, or second best
                           // with exact_margin), so the part's best stays exact and the merge is too
-  if (kb < ke) sweep_levels<FMT, KC>(a, g, v, s, vw, A, kb, ke, best, second, kbest, computed);
+  uint32_t scored = 0;
+  if (kb < ke) sweep_levels<FMT, KC>(a, g, v, s, vw, A, kb, ke, best, second, kbest, computed, scored);
   if (lane == 0) {
     parts[part] = make_float4(best, second, __int_as_float(kbest), 0.f);
     atomicAdd(&a.work[3], (unsigned long long)computed);
+    atomicAdd(&a.work[4], (unsigned long long)scored);
   }
 }
 

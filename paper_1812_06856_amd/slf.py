@@ -23,7 +23,7 @@ SLF_IMAGE_U8, SLF_IMAGE_F16, SLF_IMAGE_F32 = 0, 1, 2
 EXPORTED = [
     "slf_default_params", "slf_create", "slf_destroy", "slf_set_stream", "slf_set_params", "slf_set_cameras",
     "slf_set_neighbors", "slf_set_image_rgb8", "slf_set_labels", "slf_prepare", "slf_sweep", "slf_set_planes", "slf_propagate",
-    "slf_get_planes", "slf_get_depth", "slf_get_superpixels", "slf_get_work", "slf_get_sweep_work", "slf_reset_work", "slf_synchronize",
+    "slf_get_planes", "slf_get_depth", "slf_get_superpixels", "slf_get_work", "slf_get_sweep_work", "slf_get_sweep_levels", "slf_reset_work", "slf_synchronize",
     "slf_status_string", "slf_last_error", "slf_warm_start", "slf_get_footprint",
     "slf_fuse", "slf_get_fused_depth", "slf_fuse_depth", "slf_fuse_depth_static", "slf_segment", "slf_get_labels",
     "slf_pool_default_config", "slf_pool_create", "slf_pool_destroy", "slf_pool_set_stream", "slf_pool_set_config",
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
     L.slf_get_work.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                ctypes.POINTER(ctypes.c_uint64)]
     L.slf_get_sweep_work.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+    L.slf_get_sweep_levels.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
     L.slf_reset_work.argtypes = [P]
     L.slf_synchronize.argtypes = [P]
     L.slf_status_string.argtypes = [I]
@@ -319,6 +320,12 @@ class Context:
         c, t = ctypes.c_uint64(), ctypes.c_uint64()
         self._check(self._L.slf_get_sweep_work(self._h, ctypes.byref(c), ctypes.byref(t)))
         return int(c.value), int(t.value)
+
+    def sweep_levels(self):
+        """(sweep levels scored in full, sweep levels decided)."""
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self._L.slf_get_sweep_levels(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
 
     def work_detail(self):
         """(hypotheses decided, px-view samples computed, refinement candidates pruned)."""
