@@ -751,7 +751,7 @@ int slf_propagate(slf_ctx *c, int first_iter, int n_iters) {
   for (int it = first_iter; it < first_iter + n_iters; ++it) {
     RefineArgs a;
     refine_args(c, it, a);
-    HIP_OR_FAIL(c, launch_refine(c->p.image_precision, a, c->d_refine_args, c->stream));
+    HIP_OR_FAIL(c, launch_refine(c->p.image_precision, a, c->d_refine_args, c->d_claims, c->n_cu, c->stream));
     after_refine(c);
   }
   return SLF_OK;

@@ -140,7 +140,7 @@ hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V
 hipError_t launch_sweep(int fmt, const SweepArgs &a, int *counters, int n_cu, hipStream_t st);
 // `slot`: device memory for the refinement's arguments (written on the stream
 // before the kernel, which reads them from there).
-hipError_t launch_refine(int fmt, const RefineArgs &a, RefineArgs *slot, hipStream_t st);
+hipError_t launch_refine(int fmt, const RefineArgs &a, RefineArgs *slot, int *counters, int n_cu, hipStream_t st);
 hipError_t launch_depth(const ViewDev *views_d, const ViewDev &vh, int view, const int *labels,
                         const float4 *tab, float *out, int64_t stride, hipStream_t st);
 size_t quad_bytes(int fmt);
