@@ -426,7 +426,8 @@ __global__ __launch_bounds__(kBlock) void k_sp_fill(const ViewDev *views, const 
     const double n = (double)cnt;
     centroid_d[g] = make_double2((double)sx / n, (double)sy / n);
     centroid[g] = make_float2((float)((double)sx / n), (float)((double)sy / n));
-    colour[g] = make_float4((float)(sr / (255.0 * n)), (float)(sg / (255.0 * n)), (float)(sb / (255.0 * n)), 0.f);
+    const float cr = (float)(sr / (255.0 * n)), cg = (float)(sg / (255.0 * n)), cb = (float)(sb / (255.0 * n));
+    colour[g] = make_float4(cr, cg, cb, fmaf(cb, cb, fmaf(cg, cg, cr * cr)));  // w = |C|^2 (eq. 7's weight)
   }
 }
 
@@ -968,6 +969,12 @@ __device__ __forceinline__ float3 load_f3(__amdgpu_buffer_rsrc_t rs, int off) {
   return make_float3(v.x, v.y, v.z);
 }
 
+__device__ __forceinline__ float4 load_f4(__amdgpu_buffer_rsrc_t rs, int off) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const f4v v = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // The best plane so far (in the wave's LDS) and its depth at the centroid.
 struct BestPlane {
   double nx, ny, nz, delta, d;
@@ -1163,7 +1170,11 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
     const float i0 = (float)(gd0 * c.ub + gd1 * c.vb + gd2);  // 1 / D at the rounded centroid
     const float gu = (float)gd0, gv = (float)gd1;
     float sum = 0.f;
-    const float tol = 1.f + a.occ_tol;
+    const float tau = a.occ_tol;
+    // omega of eq. (7) as exp2(k (2 C_s . C_l - |C_l|^2 - |C_s|^2)) = exp2(-k |C_s - C_l|^2):
+    // the records carry |C_l|^2, so a sample spends three FMAs on the colour
+    const float kc = a.inv2alpha2_log2e, cw0 = -kc * c.Cs.w;
+    const float c2r = 2.f * c.Cs.x, c2g = 2.f * c.Cs.y, c2b = 2.f * c.Cs.z;
     const __amdgpu_buffer_rsrc_t px_rs = buffer_rsrc(a.px + c.poff, 8u * (uint32_t)c.A);
     for (int base = 0; base < c.N; base += kViewsPerPass) {
       const int nv = min(kViewsPerPass, c.N - base);
@@ -1263,15 +1274,16 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           else
             return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(lab_rs, (int)(4u * q.pix), 0, 0);
         };
-        auto accumulate = [&](const Proj &q, const float3 Cl, const float3 gt) {
-          const float dr = c.Cs.x - Cl.x, dg = c.Cs.y - Cl.y, db = c.Cs.z - Cl.z;
-          const float om = __builtin_amdgcn_exp2f(-fmaf(db, db, fmaf(dg, dg, dr * dr)) * a.inv2alpha2_log2e);
+        auto accumulate = [&](const Proj &q, const float4 Cl, const float3 gt) {
+          const float cl = fmaf(c2r, Cl.x, fmaf(c2g, Cl.y, fmaf(c2b, Cl.z, -Cl.w)));
+          const float om = __builtin_amdgcn_exp2f(fmaf(cl, kc, cw0));
           const float den = fmaf(gt.x, fX0 + q.dx, fmaf(gt.y, fY0 + q.dy, gt.z));  // 1 / D(p^i)
           const uint64_t back = __builtin_amdgcn_ballot_w64(!(den > 0.f));
-          // z <= D(p^i) (1 + tau)  <=>  w den <= (1 + tau) iota   (iota, den > 0)
-          const float wd = q.w * den;
-          const uint64_t vis = q.seen & (back | __builtin_amdgcn_ballot_w64(wd <= tol * q.iota));
-          const float dz = (wd - q.iota) * rcp(q.iota * den);  // z - D(p^i)
+          // z <= D(p^i) (1 + tau)  <=>  w den - iota <= tau iota   (iota, den > 0);
+          // the residual is one FMA and also the numerator of z - D(p^i)
+          const float num = fmaf(q.w, den, -q.iota);
+          const uint64_t vis = q.seen & (back | __builtin_amdgcn_ballot_w64(num <= tau * q.iota));
+          const float dz = num * rcp(q.iota * den);  // z - D(p^i)
           const float gk = __builtin_amdgcn_exp2f(-dz * dz * a.inv2sig2_log2e);
           sw += __builtin_amdgcn_inverse_ballot_w64(q.seen) ? om : 0.f;
           nX += __popcll(vis);
@@ -1290,7 +1302,7 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           Proj q = listed(p);
           q.seen &= __builtin_amdgcn_ballot_w64(in);
           const uint32_t l = label(q, narrow);
-          accumulate(q, load_f3(tab_rs, (int)(32u * l)), load_f3(tab_rs, (int)(32u * l + 16u)));
+          accumulate(q, load_f4(tab_rs, (int)(32u * l)), load_f3(tab_rs, (int)(32u * l + 16u)));
         };
         // kChains pixels per lane per pass keep that many gather chains in
         // flight; each lane still accumulates its pixels in order.  The
@@ -1306,14 +1318,15 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           for (; p0 + kChains * kWave <= n_pad; p0 += kChains * kWave) {
             Proj q[kChains];
             uint32_t l[kChains];
-            float3 C[kChains], G[kChains];
+            float4 C[kChains];
+            float3 G[kChains];
 #pragma unroll
             for (int k = 0; k < kChains; ++k) q[k] = staged(p0 + k * kWave + lane);
 #pragma unroll
             for (int k = 0; k < kChains; ++k) l[k] = label(q[k], narrow);
 #pragma unroll
             for (int k = 0; k < kChains; ++k) {
-              C[k] = load_f3(tab_rs, (int)(32u * l[k]));
+              C[k] = load_f4(tab_rs, (int)(32u * l[k]));
               G[k] = load_f3(tab_rs, (int)(32u * l[k] + 16u));
             }
 #pragma unroll
@@ -1323,7 +1336,7 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
           for (; p0 < n_pad; p0 += kWave) {
             const Proj q = staged(p0 + lane);
             const uint32_t l = label(q, narrow);
-            accumulate(q, load_f3(tab_rs, (int)(32u * l)), load_f3(tab_rs, (int)(32u * l + 16u)));
+            accumulate(q, load_f4(tab_rs, (int)(32u * l)), load_f3(tab_rs, (int)(32u * l + 16u)));
           }
           for (int p0 = c.n_lds; p0 < c.A; p0 += kWave) {
             const int p = p0 + lane;
