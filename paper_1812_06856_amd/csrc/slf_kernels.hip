@@ -495,22 +495,89 @@ __device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm
   return in ? fminf(ssd, T) : T;
 }
 
-// FP16 texels: each tap enters an FMA as an FP16 operand widened exactly
-// inside the instruction (v_fma_mix_f32), so the interpolation is the FP32
-// one with no separate conversions.
-template <>
-__device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, float w, float Wm1, float Hm1, int Wi,
-                                                          int Hi, __amdgpu_buffer_rsrc_t quads, uint32_t vbase,
-                                                          float r0, float g0, float b0, float T, bool check) {
+// The RGBA8 sample in two phases, so that a caller can issue the texel
+// loads of several samples before it waits for the first: `fetch` projects,
+// clamps and issues the 16-byte load, `finish` interpolates and scores.
+// fetch + finish performs exactly the operations of tssd_sample<SLF_FMT_U8>.
+struct U8Tap {
+  uint4 q;
+  float fx, fy;
+  bool in;
+};
+
+__device__ __forceinline__ U8Tap u8_fetch(float x, float y, float w, float Wm1, float Hm1, int Wi,
+                                          __amdgpu_buffer_rsrc_t quads, uint32_t vbase, bool check) {
+  U8Tap t;
   const float rw = rcp(w);
   const float xs = x * rw, ys = y * rw;
   const float xc = check ? __builtin_amdgcn_fmed3f(xs, 0.f, Wm1) : xs;
   const float yc = check ? __builtin_amdgcn_fmed3f(ys, 0.f, Hm1) : ys;
-  const bool in = !check || ((w > 0.f) & (xc == xs) & (yc == ys));
+  t.in = !check || ((w > 0.f) & (xc == xs) & (yc == ys));
   const int x0 = (int)xc, y0 = (int)yc;
-  const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
+  t.fx = __builtin_amdgcn_fractf(xc);
+  t.fy = __builtin_amdgcn_fractf(yc);
+  t.q = load_u4(quads, vbase + (__umul24((uint32_t)y0, (uint32_t)(Wi + 1)) + (uint32_t)x0) *
+                                   (uint32_t)kQuadBytes<SLF_FMT_U8>);
+  return t;
+}
+
+__device__ __forceinline__ float u8_finish(const U8Tap &tp, float r0, float g0, float b0, float T) {
+  const uint32_t wd[4] = {tp.q.x, tp.q.z, tp.q.y, tp.q.w};  // (x0, y0), (x0+1, y0), (x0, y0+1), (x0+1, y0+1)
+  float t[12];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    t[3 * j + 0] = (float)(wd[j] & 255u);
+    t[3 * j + 1] = (float)((wd[j] >> 8) & 255u);
+    t[3 * j + 2] = (float)((wd[j] >> 16) & 255u);
+  }
+  const float ofx = 1.f - tp.fx, ofy = 1.f - tp.fy;
+  const float w00 = ofx * ofy, w10 = tp.fx * ofy, w01 = ofx * tp.fy, w11 = tp.fx * tp.fy;
+  float b[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) b[c] = fmaf(w11, t[9 + c], fmaf(w01, t[6 + c], fmaf(w10, t[3 + c], w00 * t[c])));
+  const float d0 = r0 - b[0], d1 = g0 - b[1], d2 = b0 - b[2];
+  const float ssd = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+  return tp.in ? fminf(ssd, T) : T;
+}
+
+template <>
+__device__ __forceinline__ float tssd_sample<SLF_FMT_U8>(float x, float y, float w, float Wm1, float Hm1, int Wi,
+                                                         int Hi, __amdgpu_buffer_rsrc_t quads, uint32_t vbase,
+                                                         float r0, float g0, float b0, float T, bool check) {
+  return u8_finish(u8_fetch(x, y, w, Wm1, Hm1, Wi, quads, vbase, check), r0, g0, b0, T);
+}
+
+// FP16 texels: each tap enters an FMA as an FP16 operand widened exactly
+// inside the instruction (v_fma_mix_f32), so the interpolation is the FP32
+// one with no separate conversions.  Two phases as for RGBA8 (two 16-byte
+// loads, one per texel row).
+struct F16Tap {
+  uint4 lo, hi;
+  float fx, fy;
+  bool in;
+};
+
+__device__ __forceinline__ F16Tap f16_fetch(float x, float y, float w, float Wm1, float Hm1, int Wi,
+                                            __amdgpu_buffer_rsrc_t quads, uint32_t vbase, bool check) {
+  F16Tap t;
+  const float rw = rcp(w);
+  const float xs = x * rw, ys = y * rw;
+  const float xc = check ? __builtin_amdgcn_fmed3f(xs, 0.f, Wm1) : xs;
+  const float yc = check ? __builtin_amdgcn_fmed3f(ys, 0.f, Hm1) : ys;
+  t.in = !check || ((w > 0.f) & (xc == xs) & (yc == ys));
+  const int x0 = (int)xc, y0 = (int)yc;
+  t.fx = __builtin_amdgcn_fractf(xc);
+  t.fy = __builtin_amdgcn_fractf(yc);
   const uint32_t off = vbase + (__umul24((uint32_t)y0, (uint32_t)(Wi + 1)) + (uint32_t)x0) * 8u;
-  const uint4 lo = load_u4(quads, off), hi = load_u4(quads, off + (uint32_t)(Wi + 1) * 8u);
+  t.lo = load_u4(quads, off);
+  t.hi = load_u4(quads, off + (uint32_t)(Wi + 1) * 8u);
+  return t;
+}
+
+__device__ __forceinline__ float f16_finish(const F16Tap &tp, float r0, float g0, float b0, float T) {
+  const uint4 lo = tp.lo, hi = tp.hi;
+  const float fx = tp.fx, fy = tp.fy;
+  const bool in = tp.in;
   typedef _Float16 h2 __attribute__((ext_vector_type(2)));
   const h2 rg00 = __builtin_bit_cast(h2, lo.x), b00 = __builtin_bit_cast(h2, lo.y);
   const h2 rg10 = __builtin_bit_cast(h2, lo.z), b10 = __builtin_bit_cast(h2, lo.w);
@@ -526,6 +593,13 @@ __device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, floa
   const float d0 = r0 - br, d1 = g0 - bg, d2 = b0 - bb;
   const float ssd = fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
   return in ? fminf(ssd, T) : T;
+}
+
+template <>
+__device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, float w, float Wm1, float Hm1, int Wi,
+                                                          int Hi, __amdgpu_buffer_rsrc_t quads, uint32_t vbase,
+                                                          float r0, float g0, float b0, float T, bool check) {
+  return f16_finish(f16_fetch(x, y, w, Wm1, Hm1, Wi, quads, vbase, check), r0, g0, b0, T);
 }
 
 // Byte offset of view i's texels in the texel array (which the host keeps
@@ -615,6 +689,16 @@ static int persistent_blocks(const void *kernel, int n_cu, int S) {
 #endif
 constexpr int kBoundCheck = SLF_BOUND_CHECK;
 constexpr float kBoundMargin = 1.00001f;
+#ifndef SLF_SWEEP_BATCH
+#define SLF_SWEEP_BATCH 4
+#endif
+#ifndef SLF_SWEEP_BATCH_F16
+#define SLF_SWEEP_BATCH_F16 2
+#endif
+template <int KC>
+constexpr int kSweepBatchOf = KC < SLF_SWEEP_BATCH ? KC : SLF_SWEEP_BATCH;
+template <int KC>
+constexpr int kSweepBatchF16Of = KC < SLF_SWEEP_BATCH_F16 ? KC : SLF_SWEEP_BATCH_F16;
 
 // Chunk order.  Bounded against the best complete cost, a chunk stops early
 // once a good level is known, so a coarse pre-pass first scores one level per
@@ -773,7 +857,39 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
       const float aw = fmaf(A6, pu, fmaf(A7, pv, A8));
       // every active lane in an inner view (neighbours past the 64th are
       // never taken as inner): samples without the bounds test
-      if (__ballot(iv >= kWave || ((inner_views >> iv) & 1ull) == 0ull) == 0ull) {
+      const bool inner_pass = __ballot(iv >= kWave || ((inner_views >> iv) & 1ull) == 0ull) == 0ull;
+      if constexpr (FMT == SLF_FMT_U8 || FMT == SLF_FMT_F16) {
+        // RGBA8 and FP16: the texel loads of kSweepBatchOf<KC> levels are
+        // issued before the first is consumed (the compiler otherwise waits
+        // on each load in the bounds-tested form)
+        auto levels = [&](bool check) {
+          constexpr int B = FMT == SLF_FMT_U8 ? kSweepBatchOf<KC> : kSweepBatchF16Of<KC>;
+#pragma unroll
+          for (int k0 = 0; k0 < KC; k0 += B) {
+            if constexpr (FMT == SLF_FMT_U8) {
+              U8Tap t[B];
+#pragma unroll
+              for (int j = 0; j < B; ++j)
+                t[j] = u8_fetch(fmaf(q[k0 + j], bx, ax), fmaf(q[k0 + j], by, ay), fmaf(q[k0 + j], bw, aw), Wm1, Hm1,
+                                Wi, qrs, qbase, check);
+#pragma unroll
+              for (int j = 0; j < B; ++j) acc[k0 + j] += u8_finish(t[j], r0, g0, b0, a.T255);
+            } else {
+              F16Tap t[B];
+#pragma unroll
+              for (int j = 0; j < B; ++j)
+                t[j] = f16_fetch(fmaf(q[k0 + j], bx, ax), fmaf(q[k0 + j], by, ay), fmaf(q[k0 + j], bw, aw), Wm1, Hm1,
+                                 Wi, qrs, qbase, check);
+#pragma unroll
+              for (int j = 0; j < B; ++j) acc[k0 + j] += f16_finish(t[j], r0, g0, b0, a.T255);
+            }
+          }
+        };
+        if (inner_pass)
+          levels(false);
+        else
+          levels(true);
+      } else if (inner_pass) {
 #pragma unroll
         for (int kk = 0; kk < KC; ++kk)
           acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi,
