@@ -609,6 +609,58 @@ __device__ __forceinline__ uint32_t quad_base(const ViewDev &vi) {
   return (uint32_t)vi.quad_off * (uint32_t)kQuadBytes<FMT>;
 }
 
+// levels whose texel loads are issued together (RGBA8: 4; FP16, two loads each: 2)
+#ifndef SLF_SWEEP_BATCH
+#define SLF_SWEEP_BATCH 4
+#endif
+#ifndef SLF_SWEEP_BATCH_F16
+#define SLF_SWEEP_BATCH_F16 2
+#endif
+template <int KC>
+constexpr int kSweepBatchOf = KC < SLF_SWEEP_BATCH ? KC : SLF_SWEEP_BATCH;
+template <int KC>
+constexpr int kSweepBatchF16Of = KC < SLF_SWEEP_BATCH_F16 ? KC : SLF_SWEEP_BATCH_F16;
+
+// acc[k] += the sample of one pixel in one view at levels q[0..KC): the
+// homogeneous position is (ax, ay, aw) + q (bx, by, bw).  For RGBA8 and FP16
+// texels the loads of a batch of levels are issued before the first is
+// consumed (with one sample after another the compiler waits on each load
+// in the bounds-tested form); the arithmetic of each sample is unchanged.
+template <int FMT, int KC>
+__device__ __forceinline__ void sample_levels(const float (&q)[KC], float (&acc)[KC], float ax, float ay, float aw,
+                                              float bx, float by, float bw, float Wm1, float Hm1, int Wi, int Hi,
+                                              __amdgpu_buffer_rsrc_t qrs, uint32_t qbase, float r0, float g0,
+                                              float b0, float T, bool check) {
+  if constexpr (FMT == SLF_FMT_U8 || FMT == SLF_FMT_F16) {
+    constexpr int B = FMT == SLF_FMT_U8 ? kSweepBatchOf<KC> : kSweepBatchF16Of<KC>;
+#pragma unroll
+    for (int k0 = 0; k0 < KC; k0 += B) {
+      if constexpr (FMT == SLF_FMT_U8) {
+        U8Tap t[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+          t[j] = u8_fetch(fmaf(q[k0 + j], bx, ax), fmaf(q[k0 + j], by, ay), fmaf(q[k0 + j], bw, aw), Wm1, Hm1, Wi, qrs,
+                          qbase, check);
+#pragma unroll
+        for (int j = 0; j < B; ++j) acc[k0 + j] += u8_finish(t[j], r0, g0, b0, T);
+      } else {
+        F16Tap t[B];
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+          t[j] = f16_fetch(fmaf(q[k0 + j], bx, ax), fmaf(q[k0 + j], by, ay), fmaf(q[k0 + j], bw, aw), Wm1, Hm1, Wi,
+                           qrs, qbase, check);
+#pragma unroll
+        for (int j = 0; j < B; ++j) acc[k0 + j] += f16_finish(t[j], r0, g0, b0, T);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk)
+      acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi, Hi, qrs,
+                                  qbase, r0, g0, b0, T, check);
+  }
+}
+
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
 static_assert(kPoolQueues == kXcds, "one claim queue per XCD");
 
@@ -689,16 +741,6 @@ static int persistent_blocks(const void *kernel, int n_cu, int S) {
 #endif
 constexpr int kBoundCheck = SLF_BOUND_CHECK;
 constexpr float kBoundMargin = 1.00001f;
-#ifndef SLF_SWEEP_BATCH
-#define SLF_SWEEP_BATCH 4
-#endif
-#ifndef SLF_SWEEP_BATCH_F16
-#define SLF_SWEEP_BATCH_F16 2
-#endif
-template <int KC>
-constexpr int kSweepBatchOf = KC < SLF_SWEEP_BATCH ? KC : SLF_SWEEP_BATCH;
-template <int KC>
-constexpr int kSweepBatchF16Of = KC < SLF_SWEEP_BATCH_F16 ? KC : SLF_SWEEP_BATCH_F16;
 
 // Chunk order.  Bounded against the best complete cost, a chunk stops early
 // once a good level is known, so a coarse pre-pass first scores one level per
@@ -746,11 +788,8 @@ __device__ __forceinline__ bool coarse_order(const SweepArgs &a, const int g, co
         const float ax = fmaf(pg.A[0], pu, fmaf(pg.A[1], pv, pg.A[2]));
         const float ay = fmaf(pg.A[3], pu, fmaf(pg.A[4], pv, pg.A[5]));
         const float aw = fmaf(pg.A[6], pu, fmaf(pg.A[7], pv, pg.A[8]));
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk)
-          acc[kk] += tssd_sample<FMT>(fmaf(q[kk], pg.b[0], ax), fmaf(q[kk], pg.b[1], ay), fmaf(q[kk], pg.b[2], aw),
-                                      (float)(vi.W - 1), (float)(vi.H - 1), vi.W, vi.H, qrs, quad_base<FMT>(vi), r0,
-                                      g0, b0, a.T255);
+        sample_levels<FMT, KC>(q, acc, ax, ay, aw, pg.b[0], pg.b[1], pg.b[2], (float)(vi.W - 1), (float)(vi.H - 1),
+                               vi.W, vi.H, qrs, quad_base<FMT>(vi), r0, g0, b0, a.T255, true);
       }
     }
 #pragma unroll
@@ -857,49 +896,10 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
       const float aw = fmaf(A6, pu, fmaf(A7, pv, A8));
       // every active lane in an inner view (neighbours past the 64th are
       // never taken as inner): samples without the bounds test
-      const bool inner_pass = __ballot(iv >= kWave || ((inner_views >> iv) & 1ull) == 0ull) == 0ull;
-      if constexpr (FMT == SLF_FMT_U8 || FMT == SLF_FMT_F16) {
-        // RGBA8 and FP16: the texel loads of kSweepBatchOf<KC> levels are
-        // issued before the first is consumed (the compiler otherwise waits
-        // on each load in the bounds-tested form)
-        auto levels = [&](bool check) {
-          constexpr int B = FMT == SLF_FMT_U8 ? kSweepBatchOf<KC> : kSweepBatchF16Of<KC>;
-#pragma unroll
-          for (int k0 = 0; k0 < KC; k0 += B) {
-            if constexpr (FMT == SLF_FMT_U8) {
-              U8Tap t[B];
-#pragma unroll
-              for (int j = 0; j < B; ++j)
-                t[j] = u8_fetch(fmaf(q[k0 + j], bx, ax), fmaf(q[k0 + j], by, ay), fmaf(q[k0 + j], bw, aw), Wm1, Hm1,
-                                Wi, qrs, qbase, check);
-#pragma unroll
-              for (int j = 0; j < B; ++j) acc[k0 + j] += u8_finish(t[j], r0, g0, b0, a.T255);
-            } else {
-              F16Tap t[B];
-#pragma unroll
-              for (int j = 0; j < B; ++j)
-                t[j] = f16_fetch(fmaf(q[k0 + j], bx, ax), fmaf(q[k0 + j], by, ay), fmaf(q[k0 + j], bw, aw), Wm1, Hm1,
-                                 Wi, qrs, qbase, check);
-#pragma unroll
-              for (int j = 0; j < B; ++j) acc[k0 + j] += f16_finish(t[j], r0, g0, b0, a.T255);
-            }
-          }
-        };
-        if (inner_pass)
-          levels(false);
-        else
-          levels(true);
-      } else if (inner_pass) {
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk)
-          acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi,
-                                      Hi, qrs, qbase, r0, g0, b0, a.T255, false);
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < KC; ++kk)
-          acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi,
-                                      Hi, qrs, qbase, r0, g0, b0, a.T255, true);
-      }
+      if (__ballot(iv >= kWave || ((inner_views >> iv) & 1ull) == 0ull) == 0ull)
+        sample_levels<FMT, KC>(q, acc, ax, ay, aw, bx, by, bw, Wm1, Hm1, Wi, Hi, qrs, qbase, r0, g0, b0, a.T255, false);
+      else
+        sample_levels<FMT, KC>(q, acc, ax, ay, aw, bx, by, bw, Wm1, Hm1, Wi, Hi, qrs, qbase, r0, g0, b0, a.T255, true);
       p += kWave;
       while (p >= A) {
         p -= A;
