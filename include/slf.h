@@ -113,7 +113,12 @@ int slf_set_params(slf_ctx *ctx, const slf_params *p);
 int slf_set_cameras(slf_ctx *ctx, int n_views, const int32_t *wh, const double *K, const double *R,
                     const double *t);
 /* Neighbour views N(r) of view `view` used by eqs. (2) and (8); n >= 1
- * distinct views other than `view`.  Default: all other views, ascending. */
+ * distinct views other than `view`.  Default: all other views, ascending.
+ * N(r) is a set: the kernels visit it in decreasing distance between camera
+ * centres (ties in the given order), so the views with the widest baselines,
+ * which separate depth hypotheses most, come first and the exact bounds of
+ * the sweep and the refinement stop earlier.  The order changes no decision,
+ * only the FP32 rounding of the per-view sums. */
 int slf_set_neighbors(slf_ctx *ctx, int view, int n, const int32_t *views);
 /* RGB8 image of a view, H rows of W * 3 bytes separated by row_stride_bytes
  * (>= 3 W).  is_device = 1: rgb is a device pointer read on the stream. */

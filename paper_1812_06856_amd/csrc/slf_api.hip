@@ -177,7 +177,27 @@ int build_geometry(slf_ctx *c) {
     px += (int64_t)h.W * h.H;
     qd += (int64_t)(h.W + 1) * (h.H + 1);
     // pairs: A = K_i R_ri K_r^-1, b = K_i t_ri, R_ri = R_i R_r^T, t_ri = t_i - R_ri t_r
-    for (int i : h.nbrs) {
+    // N(r) in decreasing distance between camera centres (stable): the
+    // widest baselines separate depth hypotheses most, so the exact bounds
+    // of the sweep (over level chunks) and of the refinement (over views)
+    // stop earlier; the order changes only the rounding of per-view sums
+    // (full-HD sweep 20.3 -> 19.5 ms, refinement 27.1 -> 26.7 ms)
+    std::vector<int> order = h.nbrs;
+    {
+      auto centre = [&](const ViewHost &q, double *C) {
+        for (int a = 0; a < 3; ++a) C[a] = -(q.R[a] * q.t[0] + q.R[3 + a] * q.t[1] + q.R[6 + a] * q.t[2]);
+      };
+      double Cr[3];
+      centre(h, Cr);
+      std::vector<double> dist(c->V, 0.0);
+      for (int i : order) {
+        double Ci[3];
+        centre(c->vh[i], Ci);
+        dist[i] = (Ci[0] - Cr[0]) * (Ci[0] - Cr[0]) + (Ci[1] - Cr[1]) * (Ci[1] - Cr[1]) + (Ci[2] - Cr[2]) * (Ci[2] - Cr[2]);
+      }
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return dist[x] > dist[y]; });
+    }
+    for (int i : order) {
       const ViewHost &hi = c->vh[i];
       double RrT[9], Rri[9], tri[3], T1[9], A[9];
       for (int a = 0; a < 3; ++a)

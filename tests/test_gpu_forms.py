@@ -285,17 +285,22 @@ def test_served_frames_equal_alone_and_in_the_mix():
 
 
 def test_autotune_caches_and_keeps_results():
+    """The autotuner's trials leave every rig as after a plain sweep.  With
+    the default bound the reported margins are upper bounds whose value
+    depends on the level chunk and split the autotuner picks, so the rigs
+    run with exact margins here: every output is then independent of the
+    schedule and must equal the plain sweep's bit for bit."""
     slf = _slf()
     _say("autotune")
     ws = _rigs()[:2]
     swept = []
     for w in ws:
-        c = _ctx(w)
+        c = _ctx(w, exact_margin=1)
         c.sweep()
         swept.append(_state(c, len(w.rig.views)))
         c.close()
     pool = slf.Pool(0)
-    ctxs = [_ctx(w) for w in ws]
+    ctxs = [_ctx(w, exact_margin=1) for w in ws]
     for c in ctxs:
         pool.attach(c)
     w0 = [c.work() for c in ctxs]
