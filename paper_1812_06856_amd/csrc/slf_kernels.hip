@@ -1079,6 +1079,10 @@ constexpr int kLdsPix = 1024;  // pixels of a superpixel staged in LDS (the rest
 // faster than 2 on the full-HD refinement, the extra registers spilling only
 // outside the sample loops
 constexpr int kChains = SLF_REFINE_CHAINS;
+#ifndef SLF_REFINE_WAVES
+#define SLF_REFINE_WAVES 5
+#endif
+constexpr int kRefineWaves = SLF_REFINE_WAVES;  // waves per SIMD the refinement's registers are sized for
 static_assert(kLdsPix % kWave == 0, "the staged pixel list pads to whole waves");
 
 typedef __attribute__((address_space(3))) uint32_t LdsU32;
@@ -1791,7 +1795,7 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Wave
 // the claim loop takes a frame from 58.1 to 52.7 ms; with the arguments read
 // through the constant address space the loop fits in 96 VGPRs).
 template <int FMT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_refine(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kRefineWaves))) void k_refine(
     const RefineArgs *__restrict__ args, int *__restrict__ counters) {
   __shared__ WaveLds s_wave[kWavesPerBlock];
   // The arguments sit in device memory, read through the constant address
@@ -1826,7 +1830,7 @@ hipError_t launch_refine(int fmt, const RefineArgs &a, RefineArgs *slot, int *co
 typedef const __attribute__((address_space(4))) PoolStage ConstStage;
 
 template <int OP, int FMT, int KC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SLF_OP_REFINE ? 5 : 1))) void k_pool(const PoolStage *__restrict__ stage_ptr, int *__restrict__ counters) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SLF_OP_REFINE ? kRefineWaves : 1))) void k_pool(const PoolStage *__restrict__ stage_ptr, int *__restrict__ counters) {
   __shared__ WaveLds s_wave[OP == SLF_OP_REFINE ? kWavesPerBlock : 1];
   // The stage table does not change during the launch: read it through the
   // constant address space, as kernel arguments are, so that its fields are
