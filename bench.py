@@ -107,6 +107,8 @@ def parse():
                     help="serving: p99 bound defining the sustained rate reported as value")
     ap.add_argument("--serve-seed", type=int, default=5)
     ap.add_argument("--image-precision", type=int, default=0)
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="run the VALU issue-rate probe (paper_1812_06856_amd/_build/issue_rates) and exit")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -192,6 +194,13 @@ def main():
     if args.gpus != 1:
         print("bench.py: runs on one GPU only; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.issue_rates:
+        import subprocess
+
+        probe = os.path.join(ROOT, "paper_1812_06856_amd", "_build", "issue_rates")
+        if not os.path.exists(probe):
+            sys.exit("bench.py: %s is not built (paper_1812_06856_amd/build.py builds it)" % probe)
+        sys.exit(subprocess.run([probe]).returncode)
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib)
         return
@@ -475,7 +484,13 @@ def run_precision(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "views": V, "resolution": "1280x720", "levels": p.levels,
                    "iterations": p.iterations, "image_storage": "f16", "parallelism": "none"},
-        "forms": forms, "f16_vs_f32_speedup": forms["f32"]["ms_per_frame"] / forms["f16"]["ms_per_frame"],
+        "forms": forms,
+        # the plain path stores its 8-bit images exactly as RGBA8 texels (u8): that is the form to beat;
+        # a ratio below 1 means the FP16 form is slower
+        "plain_storage": "u8",
+        "f16_vs_u8_speedup": forms["u8"]["ms_per_frame"] / forms["f16"]["ms_per_frame"],
+        "pooled_f16_vs_solo_u8_speedup": forms["u8"]["ms_per_frame"] / forms["f16"]["pooled_ms_per_frame"],
+        "f16_vs_f32_storage_speedup": forms["f32"]["ms_per_frame"] / forms["f16"]["ms_per_frame"],
         "oracle_reference": os.path.relpath(ref_path, ROOT) if orc_depth is not None else None,
     }
     print(json.dumps(out), flush=True)

@@ -46,6 +46,13 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # the VALU issue-rate probe (bench.py --issue-rates), a separate executable
+    probe = os.path.join(OUT_DIR, "issue_rates")
+    cmd = [hipcc, *HIPCC_FLAGS, "-x", "hip", os.path.join(CSRC, "issue_rates.hip"), "-o", probe + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(probe + ".tmp", probe)
     return LIB
 
 
