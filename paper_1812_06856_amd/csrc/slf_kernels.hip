@@ -1086,6 +1086,8 @@ constexpr int kRefineWaves = SLF_REFINE_WAVES;  // waves per SIMD the refinement
 static_assert(kLdsPix % kWave == 0, "the staged pixel list pads to whole waves");
 
 typedef __attribute__((address_space(3))) uint32_t LdsU32;
+typedef __attribute__((address_space(3))) float LdsF32;
+typedef __attribute__((address_space(3))) uint8_t LdsU8;
 
 __device__ __forceinline__ float3 load_f3(__amdgpu_buffer_rsrc_t rs, int off) {
   typedef float f3v __attribute__((ext_vector_type(3)));
@@ -1109,6 +1111,7 @@ typedef __attribute__((address_space(3))) BestPlane LdsBest;
 struct Best {
   float E, second;
   int slot, evaluated, pruned, view_samples;
+  bool ordered;  // views are visited in the order of the first candidate's terms (vorder)
 };
 
 // Ring neighbour j of the superpixel (eq. 5), held in LDS.
@@ -1191,6 +1194,8 @@ struct SpCtx {
   const LdsRing *ring;       // ring neighbours 0..7
   LdsViewConst *vc;          // constants of up to kViewsPerPass neighbour views
   LdsBest *best;             // plane of the running winner
+  LdsF32 *tview;             // per-view terms of the first evaluated candidate (N <= kViewsPerPass)
+  LdsU8 *vorder;             // views in increasing order of those terms
   double rsx, rsy, rsz;      // K_r^-1 (c_s, 1)
   float4 Cs;                 // mean colour
   float omega_min;           // min over ring neighbours of omega(C_s, C_j); 1 without neighbours
@@ -1219,7 +1224,7 @@ __device__ __forceinline__ double bcast_d(double x, int l) {
 // number of neighbour views sampled.
 template <int FMT>
 __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, double nx, double ny, double nz,
-                        double delta, float e_floor, bool &pruned, int &views) {
+                        double delta, float e_floor, bool &pruned, int &views, bool record, bool ordered) {
   pruned = false;
   views = 0;
   const int lane = threadIdx.x & (kWave - 1);
@@ -1335,8 +1340,9 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         lds_put(c.vc + lane, ViewConst{ax, axu, axv, ay, ayu, ayv, aw, awu, awv, X0, Y0, 0});
       }
       wave_lds_sync();
-      for (int jv = 0; jv < nv; ++jv) {
-        // view base + jv's constants, uniform over the wave
+      for (int jo = 0; jo < nv; ++jo) {
+        // the jo-th view of this pass (in vorder once it is set), uniform over the wave
+        const int jv = ordered ? __builtin_amdgcn_readfirstlane((int)c.vorder[jo]) : jo;
         const ViewConst q = lds_get(c.vc + jv);
         // The multipliers go to scalar registers.  The three addends stay
         // in vector registers (every lane read the same LDS word): an FMA
@@ -1477,7 +1483,9 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         const bool Y = occluded != 0ull;
         const float Si = swt * c.invA;
         const float Vi = nXt > 0 ? Si * gxt * rcp((float)nXt) : 0.f;
-        sum += Vi + (Y ? occ : 0.f);
+        const float term = Vi + (Y ? occ : 0.f);
+        if (record && lane == 0) c.tview[base + jv] = term;
+        sum += term;
         ++views;
         const float left = (float)(c.N - views);
         if (Es * (sum + left * (1.f + occ)) * rcp((float)c.N) * 1.001f < e_floor) {
@@ -1539,7 +1547,31 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
     // best (a strictly larger energy does), nor tie with it; with exact_margin
     // the floor is the second best, so it cannot be the second best either.
     const float floor_E = a.exact_margin ? b.second : (b.slot >= 0 ? b.E : -INFINITY);
-    const float E = uni_f(energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta, floor_E, pruned, views));
+    // The first candidate (never pruned: the floor is still -inf) records its
+    // per-view terms of E_c; later candidates visit the views in increasing
+    // order of those terms.  Views where even the running winner scores low
+    // (pixels outside the image, occluded, or in other superpixels) bring a
+    // candidate's bound down fastest; the bound holds in any order, and only
+    // the FP32 rounding order of the view sum changes.
+    const bool record = !b.ordered && b.evaluated == 0 && a.energy_mode == 0 && (a.term_mask & 2u) &&
+                        c.N <= kViewsPerPass;
+    const float E =
+        uni_f(energy<FMT>(a, c, vw, cd.nx, cd.ny, cd.nz, cd.delta, floor_E, pruned, views, record, b.ordered));
+    if (record && !pruned && views == c.N) {
+      wave_lds_sync();
+      const int lane = threadIdx.x & (kWave - 1);
+      if (lane < c.N) {
+        const float t = c.tview[lane];
+        int rank = 0;
+        for (int j = 0; j < c.N; ++j) {
+          const float u = c.tview[j];
+          rank += (u < t || (u == t && j < lane)) ? 1 : 0;
+        }
+        c.vorder[rank] = (uint8_t)lane;
+      }
+      wave_lds_sync();
+      b.ordered = true;
+    }
     ++b.evaluated;
     b.view_samples += views;
     if (pruned) {  // bounded below the second best: no change
@@ -1567,6 +1599,8 @@ __device__ void evaluate(const RefineArgs &a, const SpCtx &c, const ViewDev &vw,
 // evaluated in that order by one energy loop.
 // The LDS space of one wave in the refinement.
 struct WaveLds {
+  float tview[kViewsPerPass];
+  uint8_t vorder[kViewsPerPass];
   Cand list[kCandBatch];
   uint32_t pix[kLdsPix];
   ViewConst vc[kViewsPerPass];
@@ -1652,6 +1686,8 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Wave
   c.ring = ring;
   c.vc = (LdsViewConst *)wl.vc;
   c.best = (LdsBest *)&wl.best;
+  c.tview = (LdsF32 *)wl.tview;
+  c.vorder = (LdsU8 *)wl.vorder;
   wave_lds_sync();
 
   Best b;
@@ -1661,6 +1697,7 @@ __device__ __forceinline__ void refine_sp(const RefineArgs &a, const int g, Wave
   b.evaluated = 0;
   b.pruned = 0;
   b.view_samples = 0;
+  b.ordered = false;
 
   // Propagation (Sec. III-C, eq. 4): slot r = 0 the current plane, 1 + j ring
   // neighbour j, 9 + 8 (m / step - 1) + j the cell m cells away along ring
