@@ -92,6 +92,7 @@ int ensure_alloc(slf_ctx *c, size_t bytes, void **ptr) {
 
 void free_sp(slf_ctx *c) {
   dfree(c->d_count);
+  dfree(c->d_order);
   dfree(c->d_sp_view);
   dfree(c->d_area);
   dfree(c->d_px_off);
@@ -238,6 +239,35 @@ int build_geometry(slf_ctx *c) {
   return SLF_OK;
 }
 
+// The order in which the per-superpixel launches claim superpixels: strips
+// of kStripCellRows grid rows, each strip over every view (raster order
+// within a view), strips top to bottom.  The claim queues cut this order into
+// one contiguous range per XCD, so an XCD works through a band of rows of
+// every view at once: what its superpixels read in the other views (their
+// texels for the sweep, their labels and plane records for the refinement)
+// lies in the same rows, shared by the reference views of the strip instead
+// of streamed once per view through that XCD's L2.  Superpixels are
+// independent within a launch, so the order changes no result.
+#ifndef SLF_STRIP_ROWS
+#define SLF_STRIP_ROWS 2
+#endif
+constexpr int kStripCellRows = SLF_STRIP_ROWS;
+std::vector<int> strip_order(const slf_ctx *c) {
+  std::vector<std::pair<int64_t, int>> key;
+  key.reserve(c->S);
+  for (int v = 0; v < c->V; ++v) {
+    const ViewDev &d = c->views_h[v];
+    for (int s = 0; s < d.gw * d.gh; ++s) {
+      const int strip = (s / d.gw) / kStripCellRows;
+      key.emplace_back(((int64_t)strip * c->V + v) * (int64_t)(1 << 24) + s, d.sp_off + s);
+    }
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int> order(key.size());
+  for (size_t i = 0; i < key.size(); ++i) order[i] = key[i].second;
+  return order;
+}
+
 // Superpixel buffers for c->S superpixels; *kept is set when the existing
 // buffers (and the plane state in them) were large enough to stay.
 int alloc_sp(slf_ctx *c, bool *kept) {
@@ -249,6 +279,7 @@ int alloc_sp(slf_ctx *c, bool *kept) {
   int rc;
   if ((rc = ensure_alloc(c, sizeof(int) * S, (void **)&c->d_count))) return rc;
   if ((rc = ensure_alloc(c, sizeof(int) * S, (void **)&c->d_sp_view))) return rc;
+  if ((rc = ensure_alloc(c, sizeof(int) * S, (void **)&c->d_order))) return rc;
   if ((rc = ensure_alloc(c, sizeof(int) * S, (void **)&c->d_area))) return rc;
   if ((rc = ensure_alloc(c, sizeof(int) * (S + 1), (void **)&c->d_px_off))) return rc;
   if ((rc = ensure_alloc(c, sizeof(int) * nb, (void **)&c->d_scan))) return rc;
@@ -316,6 +347,11 @@ int slf::ensure_setup(slf_ctx *c) {
     c->warm_ok = kept && same_cells && all_planes;
     c->lab16_ok = true;
     for (const auto &v : c->vh) c->lab16_ok = c->lab16_ok && (int64_t)v.gw * v.gh <= 65536;
+    {
+      const std::vector<int> order = strip_order(c);
+      HIP_OR_FAIL(c, hipMemcpyAsync(c->d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice,
+                                    c->stream));
+    }
     HIP_OR_FAIL(c, launch_sp_build(c->d_views, c->views_h.data(), c->V, c->d_labels,
                                    c->lab16_ok ? c->d_lab16 : nullptr, c->d_rgb, c->S, c->d_count,
                                    c->d_bbox, c->d_px_off, c->d_scan, c->d_px, c->d_area, c->d_centroid,
@@ -372,6 +408,7 @@ void slf::sweep_args(const slf_ctx *c, SweepArgs &a) {
   a.views = c->d_views;
   a.pairs = c->d_pairs;
   a.sp_view = c->d_sp_view;
+  a.order = c->d_order;
   a.area = c->d_area;
   a.px_off = c->d_px_off;
   a.px = c->d_px;
@@ -415,6 +452,7 @@ void slf::refine_args(const slf_ctx *c, int iter, RefineArgs &a) {
   a.views = c->d_views;
   a.pairs = c->d_pairs;
   a.sp_view = c->d_sp_view;
+  a.order = c->d_order;
   a.area = c->d_area;
   a.px_off = c->d_px_off;
   a.px = c->d_px;

@@ -65,6 +65,7 @@ struct slf_ctx {
   int4 *d_bbox = nullptr;
   float2 *d_centroid = nullptr;
   double2 *d_centroid_d = nullptr;
+  int *d_order = nullptr;  // claim order of the per-superpixel launches (strip order, see strip_order)
   float4 *d_colour = nullptr;
   slf::PixEntry *d_px = nullptr;
   float4 *d_planes[2] = {nullptr, nullptr};

@@ -49,6 +49,7 @@ struct SweepArgs {
   const ViewDev *views;
   const PairDev *pairs;
   const int *sp_view;
+  const int *order;     // claim c of the launch takes superpixel order[c]
   const int *area;
   const int *px_off;
   const PixEntry *px;
@@ -76,6 +77,7 @@ struct RefineArgs {
   const ViewDev *views;
   const PairDev *pairs;
   const int *sp_view;
+  const int *order;     // claim c of the launch takes superpixel order[c]
   const int *area;
   const int *px_off;
   const PixEntry *px;
