@@ -49,7 +49,7 @@ struct SweepArgs {
   const ViewDev *views;
   const PairDev *pairs;
   const int *sp_view;
-  const int *order;     // claim c of the launch takes superpixel order[c]
+  const int *order;     // claim c of the launch takes superpixel order[c] (nullptr: superpixel c)
   const int *area;
   const int *px_off;
   const PixEntry *px;
@@ -77,7 +77,7 @@ struct RefineArgs {
   const ViewDev *views;
   const PairDev *pairs;
   const int *sp_view;
-  const int *order;     // claim c of the launch takes superpixel order[c]
+  const int *order;     // claim c of the launch takes superpixel order[c] (nullptr: superpixel c)
   const int *area;
   const int *px_off;
   const PixEntry *px;

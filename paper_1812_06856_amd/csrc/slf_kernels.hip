@@ -1046,7 +1046,7 @@ constexpr int kLevelChunk = SLF_LEVEL_CHUNK;
 
 template <int FMT, int KC>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, int *__restrict__ counters) {
-  for_each_claimed(a.S, counters, [&](int c) { sweep_sp<FMT, KC>(a, ro_at(a.order, c)); });
+  for_each_claimed(a.S, counters, [&](int c) { sweep_sp<FMT, KC>(a, a.order ? ro_at(a.order, c) : c); });
 }
 
 // Writes one launch's arguments into device memory (the launch copies its
@@ -1843,7 +1843,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kRefineW
   typedef const __attribute__((address_space(4))) RefineArgs ConstRefine;
   const RefineArgs &a = *(const RefineArgs *)&*(ConstRefine *)args;
   const int wid = threadIdx.x >> 6;
-  for_each_claimed(a.S, counters, [&](int c) { refine_sp<FMT>(a, ro_at(a.order, c), s_wave[wid]); });
+  for_each_claimed(a.S, counters, [&](int c) { refine_sp<FMT>(a, a.order ? ro_at(a.order, c) : c, s_wave[wid]); });
 }
 
 hipError_t launch_refine(int fmt, const RefineArgs &a, RefineArgs *slot, int *counters, int n_cu, hipStream_t st) {
@@ -1897,8 +1897,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SL
         const int part = t % split;
         const int g0 = (t / split) * tile;
         const int g1 = min(g0 + tile, J.S);
-        for (int c = g0; c < g1; ++c) {  // claims in the rig's strip order
-          const int g = ro_at(J.sweep.order, c);
+        for (int c = g0; c < g1; ++c) {  // claims in the rig's strip order (index order without one)
+          const int g = J.sweep.order ? ro_at(J.sweep.order, c) : c;
           if (split == 1)
             sweep_sp<FMT, KC>(J.sweep, g);
           else
@@ -1907,7 +1907,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SL
       } else {
         const int g0 = (item - J.item_begin) * tile;
         const int g1 = min(g0 + tile, J.S);
-        for (int c = g0; c < g1; ++c) refine_sp<FMT>(J.refine, ro_at(J.refine.order, c), s_wave[wid]);
+        for (int c = g0; c < g1; ++c) refine_sp<FMT>(J.refine, J.refine.order ? ro_at(J.refine.order, c) : c, s_wave[wid]);
       }
     }
   }

@@ -164,14 +164,21 @@ void fill_stage(slf_pool *P, PoolStage &st, const Group &g, int s_cap, bool adva
     }
     sp += J.S;
     items += (J.S + tile - 1) / tile * split;
+    // A job cut to its first s_cap claims (the autotuner's timing stages)
+    // takes superpixels 0..J.S-1 in index order: its split-sweep part
+    // records are reserved for J.S superpixels and addressed by superpixel,
+    // and the rig's strip order would reach superpixels past J.S.
+    const bool capped = J.S < r->rig->S;
     if (g.op == SLF_OP_SWEEP) {
       sweep_args(r->rig, J.sweep);
+      if (capped) J.sweep.order = nullptr;
       if (advance) {
         after_sweep(r->rig);
         r->sweep = false;
       }
     } else {
       refine_args(r->rig, r->next_iter, J.refine);
+      if (capped) J.refine.order = nullptr;
       if (advance) {
         after_refine(r->rig);
         ++r->next_iter;

@@ -317,6 +317,37 @@ def test_autotune_caches_and_keeps_results():
     pool.close()
 
 
+def test_autotune_on_rigs_larger_than_its_trial_cap():
+    """The autotuner times stages cut to the first 2048 superpixels of each
+    rig, with level splits among the schedules it tries.  On rigs with more
+    superpixels than that, a cut stage must take superpixels 0..2047 in index
+    order (its split records are reserved for 2048 superpixels), while full
+    stages take the rig's strip order; afterwards every output equals a plain
+    sweep's."""
+    slf = _slf()
+    _say("autotune on rigs above the trial cap")
+    ws = [tiny_custom(640, 360, 64, 36, seed=41, levels=24, iterations=1, labels="grid"),
+          tiny_custom(320, 240, 50, 48, seed=42, levels=16, iterations=1, n_views=4, labels="grid")]
+    assert all(w.rig.views[0].gw * w.rig.views[0].gh * w.rig.n_views > 2048 for w in ws)
+    swept = []
+    for w in ws:
+        c = _ctx(w, exact_margin=1)
+        c.sweep()
+        swept.append(_state(c, len(w.rig.views)))
+        c.close()
+    pool = slf.Pool(0)
+    ctxs = [_ctx(w, exact_margin=1) for w in ws]
+    for c in ctxs:
+        pool.attach(c)
+    assert pool.autotune() is False
+    _say("autotuned: %s" % pool.get_config().as_dict())
+    for j, (w, c) in enumerate(zip(ws, ctxs)):
+        _same(_state(c, len(w.rig.views)), swept[j], "after autotune rig %d" % j)
+    for c in ctxs:
+        c.close()
+    pool.close()
+
+
 def test_pool_argument_errors():
     slf = _slf()
     _say("pool errors")
