@@ -1439,9 +1439,9 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         // staged list is padded to whole waves with NaN offsets: a NaN pixel
         // projects to iota = NaN, so it is never seen and adds +0, which
         // leaves the lane's sums unchanged, and its clamped gathers stay in
-        // bounds.  The trip counts are uniform (whole passes, then at most
-        // one wave of pixels on one chain), and the wave-level counts stay in
-        // scalar registers.
+        // bounds.  The trip counts are uniform (whole passes, then fewer than
+        // kChains waves of pixels on one chain), and the wave-level counts
+        // stay in scalar registers.
         auto samples = [&](auto narrow) {
           const int n_pad = c.n_pad;
           int p0 = 0;
@@ -1462,7 +1462,7 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
 #pragma unroll
             for (int k = 0; k < kChains; ++k) accumulate(q[k], C[k], G[k]);
           }
-          // the staged list pads to whole waves: a last wave of pixels takes one chain
+          // the staged list pads to whole waves: the waves left after the whole passes take one chain
           for (; p0 < n_pad; p0 += kWave) {
             const Proj q = staged(p0 + lane);
             const uint32_t l = label(q, narrow);
