@@ -151,6 +151,14 @@ __device__ __forceinline__ int round_half_up(float x) {
   return r;
 }
 
+// floor(x) as an integer in one instruction (v_cvt_flr_i32_f32; a NaN gives
+// 0).  The compiler emits a floor and a conversion for (int)floorf(x).
+__device__ __forceinline__ int floor_to_int(float x) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 // Lane `l`'s value, uniform over the wave (l must be wave-uniform).
 __device__ __forceinline__ float bcast(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
@@ -455,6 +463,45 @@ hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V
 }
 
 // ------------------------------------------------------------------ sweep sample
+// Byte offset of view i's texels in the texel array (which the host keeps
+// under 4 GiB, so that one wave-uniform buffer resource covers every view).
+template <int FMT>
+__device__ __forceinline__ uint32_t quad_base(const ViewDev &vi) {
+  return (uint32_t)vi.quad_off * (uint32_t)kQuadBytes<FMT>;
+}
+
+// Where the samples in one neighbour view land.  Positions are taken relative
+// to an integer pixel (X0, Y0) of that view (0 for absolute positions), so
+// that the FP32 per-sample arithmetic works on small numbers at any image
+// size: the image [0, W-1] x [0, H-1] is [xlo, xhi] x [ylo, yhi] in these
+// coordinates, and vbase is the byte offset of texel entry (X0, Y0), modulo
+// 2^32 like every offset formed from it (the texel array is below 4 GiB).
+struct SampleFrame {
+  float xlo, xhi, ylo, yhi;
+  int Wi;  // view width: a texel row holds W + 1 entries
+  uint32_t vbase;
+};
+
+template <int FMT>
+__device__ __forceinline__ SampleFrame frame_at(const ViewDev &vi, int X0, int Y0) {
+  SampleFrame f;
+  f.xlo = (float)(-X0);
+  f.xhi = (float)(vi.W - 1 - X0);
+  f.ylo = (float)(-Y0);
+  f.yhi = (float)(vi.H - 1 - Y0);
+  f.Wi = vi.W;
+  f.vbase = quad_base<FMT>(vi) + ((uint32_t)Y0 * (uint32_t)(vi.W + 1) + (uint32_t)X0) * (uint32_t)kQuadBytes<FMT>;
+  return f;
+}
+
+// Byte offset of texel entry (X0 + x0, Y0 + y0).  |x0|, |y0| < 2^16 and
+// W + 1 <= 2^16, so the signed 24-bit multiply (full rate) forms the index;
+// its low 32 bits are all the modular offset needs.
+template <int FMT>
+__device__ __forceinline__ uint32_t texel_offset(const SampleFrame &f, int x0, int y0) {
+  return f.vbase + (uint32_t)(__mul24(y0, f.Wi + 1) + x0) * (uint32_t)kQuadBytes<FMT>;
+}
+
 // One px-view sample of eq. (1): homogeneous projection (x, y, w), bilinear
 // RGB of the neighbour image, SSD against the reference colour, truncation.
 // Samples behind the camera or outside [0, W-1] x [0, H-1] cost T.  The texel
@@ -465,25 +512,23 @@ hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V
 // image (see sweep_levels): the clamp would be the identity, so it and the
 // test are skipped and the result is the same.
 template <int FMT>
-__device__ __forceinline__ float tssd_sample(float x, float y, float w, float Wm1, float Hm1, int Wi, int Hi,
-                                             __amdgpu_buffer_rsrc_t quads, uint32_t vbase, float r0, float g0,
-                                             float b0, float T, bool check = true) {
+__device__ __forceinline__ float tssd_sample(float x, float y, float w, const SampleFrame &f,
+                                             __amdgpu_buffer_rsrc_t quads, float r0, float g0, float b0, float T,
+                                             bool check = true) {
   const float rw = rcp(w);
   const float xs = x * rw, ys = y * rw;
   // Clamp into the image; the sample counts only if unclamped (a NaN fails
-  // the equality, and converts to texel 0, so the load stays in bounds).
-  const float xc = check ? __builtin_amdgcn_fmed3f(xs, 0.f, Wm1) : xs;
-  const float yc = check ? __builtin_amdgcn_fmed3f(ys, 0.f, Hm1) : ys;
+  // the equality, and converts to entry (X0, Y0), so the load stays in bounds).
+  const float xc = check ? __builtin_amdgcn_fmed3f(xs, f.xlo, f.xhi) : xs;
+  const float yc = check ? __builtin_amdgcn_fmed3f(ys, f.ylo, f.yhi) : ys;
   const bool in = !check || ((w > 0.f) & (xc == xs) & (yc == ys));
   // Taps at floor(x) and floor(x)+1 with weight fract(x); at x = W-1 the
   // replicated column has weight 0, which equals clamping the left tap to W-2.
-  const int x0 = (int)xc, y0 = (int)yc;
+  const int x0 = floor_to_int(xc), y0 = floor_to_int(yc);
   const float fx = __builtin_amdgcn_fractf(xc), fy = __builtin_amdgcn_fractf(yc);
   float t[12];
-  const uint32_t row = (uint32_t)(Wi + 1) * (uint32_t)kQuadBytes<FMT>;
-  // image sides are below 2^16, so 24-bit multiplies (full rate) form the texel index
-  fetch_quad<FMT>(quads, vbase + (__umul24((uint32_t)y0, (uint32_t)(Wi + 1)) + (uint32_t)x0) * (uint32_t)kQuadBytes<FMT>,
-                  row, t);
+  const uint32_t row = (uint32_t)(f.Wi + 1) * (uint32_t)kQuadBytes<FMT>;
+  fetch_quad<FMT>(quads, texel_offset<FMT>(f, x0, y0), row, t);
   // bilinear weights of the four taps (FP16 taps feed mixed-precision FMAs directly)
   const float ofx = 1.f - fx, ofy = 1.f - fy;
   const float w00 = ofx * ofy, w10 = fx * ofy, w01 = ofx * fy, w11 = fx * fy;
@@ -505,19 +550,18 @@ struct U8Tap {
   bool in;
 };
 
-__device__ __forceinline__ U8Tap u8_fetch(float x, float y, float w, float Wm1, float Hm1, int Wi,
-                                          __amdgpu_buffer_rsrc_t quads, uint32_t vbase, bool check) {
+__device__ __forceinline__ U8Tap u8_fetch(float x, float y, float w, const SampleFrame &f,
+                                          __amdgpu_buffer_rsrc_t quads, bool check) {
   U8Tap t;
   const float rw = rcp(w);
   const float xs = x * rw, ys = y * rw;
-  const float xc = check ? __builtin_amdgcn_fmed3f(xs, 0.f, Wm1) : xs;
-  const float yc = check ? __builtin_amdgcn_fmed3f(ys, 0.f, Hm1) : ys;
+  const float xc = check ? __builtin_amdgcn_fmed3f(xs, f.xlo, f.xhi) : xs;
+  const float yc = check ? __builtin_amdgcn_fmed3f(ys, f.ylo, f.yhi) : ys;
   t.in = !check || ((w > 0.f) & (xc == xs) & (yc == ys));
-  const int x0 = (int)xc, y0 = (int)yc;
+  const int x0 = floor_to_int(xc), y0 = floor_to_int(yc);
   t.fx = __builtin_amdgcn_fractf(xc);
   t.fy = __builtin_amdgcn_fractf(yc);
-  t.q = load_u4(quads, vbase + (__umul24((uint32_t)y0, (uint32_t)(Wi + 1)) + (uint32_t)x0) *
-                                   (uint32_t)kQuadBytes<SLF_FMT_U8>);
+  t.q = load_u4(quads, texel_offset<SLF_FMT_U8>(f, x0, y0));
   return t;
 }
 
@@ -541,10 +585,10 @@ __device__ __forceinline__ float u8_finish(const U8Tap &tp, float r0, float g0, 
 }
 
 template <>
-__device__ __forceinline__ float tssd_sample<SLF_FMT_U8>(float x, float y, float w, float Wm1, float Hm1, int Wi,
-                                                         int Hi, __amdgpu_buffer_rsrc_t quads, uint32_t vbase,
-                                                         float r0, float g0, float b0, float T, bool check) {
-  return u8_finish(u8_fetch(x, y, w, Wm1, Hm1, Wi, quads, vbase, check), r0, g0, b0, T);
+__device__ __forceinline__ float tssd_sample<SLF_FMT_U8>(float x, float y, float w, const SampleFrame &f,
+                                                         __amdgpu_buffer_rsrc_t quads, float r0, float g0, float b0,
+                                                         float T, bool check) {
+  return u8_finish(u8_fetch(x, y, w, f, quads, check), r0, g0, b0, T);
 }
 
 // FP16 texels: each tap enters an FMA as an FP16 operand widened exactly
@@ -557,20 +601,20 @@ struct F16Tap {
   bool in;
 };
 
-__device__ __forceinline__ F16Tap f16_fetch(float x, float y, float w, float Wm1, float Hm1, int Wi,
-                                            __amdgpu_buffer_rsrc_t quads, uint32_t vbase, bool check) {
+__device__ __forceinline__ F16Tap f16_fetch(float x, float y, float w, const SampleFrame &f,
+                                            __amdgpu_buffer_rsrc_t quads, bool check) {
   F16Tap t;
   const float rw = rcp(w);
   const float xs = x * rw, ys = y * rw;
-  const float xc = check ? __builtin_amdgcn_fmed3f(xs, 0.f, Wm1) : xs;
-  const float yc = check ? __builtin_amdgcn_fmed3f(ys, 0.f, Hm1) : ys;
+  const float xc = check ? __builtin_amdgcn_fmed3f(xs, f.xlo, f.xhi) : xs;
+  const float yc = check ? __builtin_amdgcn_fmed3f(ys, f.ylo, f.yhi) : ys;
   t.in = !check || ((w > 0.f) & (xc == xs) & (yc == ys));
-  const int x0 = (int)xc, y0 = (int)yc;
+  const int x0 = floor_to_int(xc), y0 = floor_to_int(yc);
   t.fx = __builtin_amdgcn_fractf(xc);
   t.fy = __builtin_amdgcn_fractf(yc);
-  const uint32_t off = vbase + (__umul24((uint32_t)y0, (uint32_t)(Wi + 1)) + (uint32_t)x0) * 8u;
+  const uint32_t off = texel_offset<SLF_FMT_F16>(f, x0, y0);
   t.lo = load_u4(quads, off);
-  t.hi = load_u4(quads, off + (uint32_t)(Wi + 1) * 8u);
+  t.hi = load_u4(quads, off + (uint32_t)(f.Wi + 1) * 8u);
   return t;
 }
 
@@ -596,17 +640,10 @@ __device__ __forceinline__ float f16_finish(const F16Tap &tp, float r0, float g0
 }
 
 template <>
-__device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, float w, float Wm1, float Hm1, int Wi,
-                                                          int Hi, __amdgpu_buffer_rsrc_t quads, uint32_t vbase,
-                                                          float r0, float g0, float b0, float T, bool check) {
-  return f16_finish(f16_fetch(x, y, w, Wm1, Hm1, Wi, quads, vbase, check), r0, g0, b0, T);
-}
-
-// Byte offset of view i's texels in the texel array (which the host keeps
-// under 4 GiB, so that one wave-uniform buffer resource covers every view).
-template <int FMT>
-__device__ __forceinline__ uint32_t quad_base(const ViewDev &vi) {
-  return (uint32_t)vi.quad_off * (uint32_t)kQuadBytes<FMT>;
+__device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, float w, const SampleFrame &f,
+                                                          __amdgpu_buffer_rsrc_t quads, float r0, float g0, float b0,
+                                                          float T, bool check) {
+  return f16_finish(f16_fetch(x, y, w, f, quads, check), r0, g0, b0, T);
 }
 
 // levels whose texel loads are issued together (RGBA8: 4; FP16, two loads each: 2)
@@ -628,9 +665,9 @@ constexpr int kSweepBatchF16Of = KC < SLF_SWEEP_BATCH_F16 ? KC : SLF_SWEEP_BATCH
 // in the bounds-tested form); the arithmetic of each sample is unchanged.
 template <int FMT, int KC>
 __device__ __forceinline__ void sample_levels(const float (&q)[KC], float (&acc)[KC], float ax, float ay, float aw,
-                                              float bx, float by, float bw, float Wm1, float Hm1, int Wi, int Hi,
-                                              __amdgpu_buffer_rsrc_t qrs, uint32_t qbase, float r0, float g0,
-                                              float b0, float T, bool check) {
+                                              float bx, float by, float bw, const SampleFrame &f,
+                                              __amdgpu_buffer_rsrc_t qrs, float r0, float g0, float b0, float T,
+                                              bool check) {
   if constexpr (FMT == SLF_FMT_U8 || FMT == SLF_FMT_F16) {
     constexpr int B = FMT == SLF_FMT_U8 ? kSweepBatchOf<KC> : kSweepBatchF16Of<KC>;
 #pragma unroll
@@ -639,16 +676,14 @@ __device__ __forceinline__ void sample_levels(const float (&q)[KC], float (&acc)
         U8Tap t[B];
 #pragma unroll
         for (int j = 0; j < B; ++j)
-          t[j] = u8_fetch(fmaf(q[k0 + j], bx, ax), fmaf(q[k0 + j], by, ay), fmaf(q[k0 + j], bw, aw), Wm1, Hm1, Wi, qrs,
-                          qbase, check);
+          t[j] = u8_fetch(fmaf(q[k0 + j], bx, ax), fmaf(q[k0 + j], by, ay), fmaf(q[k0 + j], bw, aw), f, qrs, check);
 #pragma unroll
         for (int j = 0; j < B; ++j) acc[k0 + j] += u8_finish(t[j], r0, g0, b0, T);
       } else {
         F16Tap t[B];
 #pragma unroll
         for (int j = 0; j < B; ++j)
-          t[j] = f16_fetch(fmaf(q[k0 + j], bx, ax), fmaf(q[k0 + j], by, ay), fmaf(q[k0 + j], bw, aw), Wm1, Hm1, Wi,
-                           qrs, qbase, check);
+          t[j] = f16_fetch(fmaf(q[k0 + j], bx, ax), fmaf(q[k0 + j], by, ay), fmaf(q[k0 + j], bw, aw), f, qrs, check);
 #pragma unroll
         for (int j = 0; j < B; ++j) acc[k0 + j] += f16_finish(t[j], r0, g0, b0, T);
       }
@@ -656,8 +691,8 @@ __device__ __forceinline__ void sample_levels(const float (&q)[KC], float (&acc)
   } else {
 #pragma unroll
     for (int kk = 0; kk < KC; ++kk)
-      acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), Wm1, Hm1, Wi, Hi, qrs,
-                                  qbase, r0, g0, b0, T, check);
+      acc[kk] += tssd_sample<FMT>(fmaf(q[kk], bx, ax), fmaf(q[kk], by, ay), fmaf(q[kk], bw, aw), f, qrs, r0, g0, b0, T,
+                                  check);
   }
 }
 
@@ -742,6 +777,79 @@ static int persistent_blocks(const void *kernel, int n_cu, int S) {
 constexpr int kBoundCheck = SLF_BOUND_CHECK;
 constexpr float kBoundMargin = 1.00001f;
 
+// Sweep constants of one (superpixel, neighbour view) pair.  Pixel offsets
+// (du, dv) from the centre (ub, vb) of the superpixel's bounding box go in,
+// and positions relative to (X0, Y0), the pixel nearest the box centre's
+// projection at the middle of the inverse-depth range, come out:
+//   x - X0 = (h0 du + h1 dv + h2 + q bx) / (h6 du + h7 dv + h8 + q bw),
+// and y - Y0 likewise with h3..h5 and by.  Row x is row x of A minus X0 times
+// row w (row y with Y0), moved to (ub, vb); the rows are composed in FP64 from
+// the pair's A and b and then rounded, so every FP32 quantity of a sample is
+// of the size of the superpixel and its disparity range, not of the image.
+struct alignas(16) SweepPair {
+  float h[9];
+  float b[3];
+  SampleFrame f;
+  int pad[2];
+};
+
+// The pixel of view i nearest (hx, hy) / hw, clamped into the image; (0, 0)
+// unless hw > 0.  Any pixel near the projection serves as a re-centring
+// pixel, so FP32 suffices (a NaN fails both tests and gives 0).
+__device__ __forceinline__ void near_pixel(double hx, double hy, double hw, const ViewDev &vi, int &X0, int &Y0) {
+  X0 = Y0 = 0;
+  if (hw > 0.0) {
+    const float r = rcp((float)hw);
+    const float cx = rintf((float)hx * r), cy = rintf((float)hy * r);
+    X0 = cx > 0.f ? (cx < (float)(vi.W - 1) ? (int)cx : vi.W - 1) : 0;
+    Y0 = cy > 0.f ? (cy < (float)(vi.H - 1) ? (int)cy : vi.H - 1) : 0;
+  }
+}
+
+template <int FMT>
+__device__ __forceinline__ SweepPair sweep_pair(const PairDev &pg, const ViewDev &vi, int ub, int vb, double qm) {
+  const double hx = pg.A_d[0] * ub + pg.A_d[1] * vb + pg.A_d[2];
+  const double hy = pg.A_d[3] * ub + pg.A_d[4] * vb + pg.A_d[5];
+  const double hw = pg.A_d[6] * ub + pg.A_d[7] * vb + pg.A_d[8];
+  int X0, Y0;
+  near_pixel(hx + qm * pg.b_d[0], hy + qm * pg.b_d[1], hw + qm * pg.b_d[2], vi, X0, Y0);
+  SweepPair p;
+  p.h[0] = (float)(pg.A_d[0] - X0 * pg.A_d[6]);
+  p.h[1] = (float)(pg.A_d[1] - X0 * pg.A_d[7]);
+  p.h[2] = (float)(hx - X0 * hw);
+  p.h[3] = (float)(pg.A_d[3] - Y0 * pg.A_d[6]);
+  p.h[4] = (float)(pg.A_d[4] - Y0 * pg.A_d[7]);
+  p.h[5] = (float)(hy - Y0 * hw);
+  p.h[6] = (float)pg.A_d[6];
+  p.h[7] = (float)pg.A_d[7];
+  p.h[8] = (float)hw;
+  p.b[0] = (float)(pg.b_d[0] - X0 * pg.b_d[2]);
+  p.b[1] = (float)(pg.b_d[1] - Y0 * pg.b_d[2]);
+  p.b[2] = (float)pg.b_d[2];
+  p.f = frame_at<FMT>(vi, X0, Y0);
+  p.pad[0] = p.pad[1] = 0;
+  return p;
+}
+
+// The pairs of the superpixel a wave sweeps: the first kSweepPairsLds are
+// composed once per superpixel, one per lane, into the wave's LDS; a
+// superpixel with more neighbour views composes the others where a lane
+// reaches them.
+constexpr int kSweepPairsLds = kWave;
+struct SweepPairs {
+  const SweepPair *lds;
+  const SweepArgs *a;
+  const ViewDev *vw;
+  int ub, vb;
+  double qm;
+  template <int FMT>
+  __device__ __forceinline__ SweepPair at(int iv) const {
+    if (iv < kSweepPairsLds) return lds[iv];
+    const PairDev &pg = a->pairs[vw->pair_off + iv];
+    return sweep_pair<FMT>(pg, a->views[pg.i], ub, vb, qm);
+  }
+};
+
 // Chunk order.  Bounded against the best complete cost, a chunk stops early
 // once a good level is known, so a coarse pre-pass first scores one level per
 // chunk (its middle one) on every kCoarseStride-th pixel pass, and the chunks
@@ -759,7 +867,7 @@ constexpr int kCoarseStride = SLF_COARSE_STRIDE;  // 0: chunks in level order
 template <int FMT, int KC>
 __device__ __forceinline__ bool coarse_order(const SweepArgs &a, const int g, const int v, const int s,
                                              const ViewDev &vw, const int A, const int k_begin, const int k_end,
-                                             uint8_t *order, uint64_t &computed) {
+                                             const SweepPairs &pairs, uint8_t *order, uint64_t &computed) {
   const int lane = threadIdx.x & (kWave - 1);
   const int P = A * vw.n_pairs;
   const int n_pass = (P + kWave - 1) / kWave;
@@ -780,16 +888,14 @@ __device__ __forceinline__ bool coarse_order(const SweepArgs &a, const int g, co
       const int j = lane + it * kWave;
       if (j < P) {
         const int iv = j / A, p = j - iv * A;
-        const PairDev &pg = a.pairs[vw.pair_off + iv];
-        const ViewDev &vi = a.views[pg.i];
+        const SweepPair sp = pairs.at<FMT>(iv);
         const PixEntry e = a.px[poff + p];
-        const float pu = (float)(e.x & 0xffffu), pv = (float)(e.x >> 16);
+        const float du = (float)((int)(e.x & 0xffffu) - pairs.ub), dv = (float)((int)(e.x >> 16) - pairs.vb);
         const float r0 = (float)(e.y & 255u), g0 = (float)((e.y >> 8) & 255u), b0 = (float)((e.y >> 16) & 255u);
-        const float ax = fmaf(pg.A[0], pu, fmaf(pg.A[1], pv, pg.A[2]));
-        const float ay = fmaf(pg.A[3], pu, fmaf(pg.A[4], pv, pg.A[5]));
-        const float aw = fmaf(pg.A[6], pu, fmaf(pg.A[7], pv, pg.A[8]));
-        sample_levels<FMT, KC>(q, acc, ax, ay, aw, pg.b[0], pg.b[1], pg.b[2], (float)(vi.W - 1), (float)(vi.H - 1),
-                               vi.W, vi.H, qrs, quad_base<FMT>(vi), r0, g0, b0, a.T255, true);
+        const float ax = fmaf(sp.h[0], du, fmaf(sp.h[1], dv, sp.h[2]));
+        const float ay = fmaf(sp.h[3], du, fmaf(sp.h[4], dv, sp.h[5]));
+        const float aw = fmaf(sp.h[6], du, fmaf(sp.h[7], dv, sp.h[8]));
+        sample_levels<FMT, KC>(q, acc, ax, ay, aw, sp.b[0], sp.b[1], sp.b[2], sp.f, qrs, r0, g0, b0, a.T255, true);
       }
     }
 #pragma unroll
@@ -822,8 +928,18 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
   const int poff = a.px_off[g];
   const int4 bb = ro_at(a.bbox, g);  // pixel bounding box (x0, y0, x1, y1)
   __shared__ uint8_t s_order[kWavesPerBlock][kWave];  // chunk order of each wave of the workgroup
+  __shared__ SweepPair s_pairs[kWavesPerBlock][kSweepPairsLds];  // pair constants of each wave's superpixel
   uint8_t *order = s_order[threadIdx.x >> 6];
-  const bool ordered = coarse_order<FMT, KC>(a, g, v, s, vw, A, k_begin, k_end, order, computed);
+  SweepPair *lds_pairs = s_pairs[threadIdx.x >> 6];
+  const SweepPairs pairs{lds_pairs, &a, &vw, (bb.x + bb.z) >> 1, (bb.y + bb.w) >> 1,
+                         a.qmin + a.dq * (0.5 * (double)a.levels)};
+  wave_lds_sync();  // the previous superpixel's reads are done
+  if (lane < min(N, kSweepPairsLds)) {
+    const PairDev &pg = a.pairs[vw.pair_off + lane];
+    lds_pairs[lane] = sweep_pair<FMT>(pg, a.views[pg.i], pairs.ub, pairs.vb, pairs.qm);
+  }
+  wave_lds_sync();
+  const bool ordered = coarse_order<FMT, KC>(a, g, v, s, vw, A, k_begin, k_end, pairs, order, computed);
   const int n_chunks = (k_end - k_begin + KC - 1) / KC;
   for (int ci = 0; ci < n_chunks; ++ci) {
     const int k0 = k_begin + KC * (ordered ? __builtin_amdgcn_readfirstlane((int)order[ci]) : ci);
@@ -864,42 +980,29 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
       ++iv;
     }
     int cur = -1;
-    float A0 = 0, A1 = 0, A2 = 0, A3 = 0, A4 = 0, A5 = 0, A6 = 0, A7 = 0, A8 = 0, bx = 0, by = 0, bw = 0;
-    float Wm1 = 0, Hm1 = 0;
-    int Wi = 2, Hi = 2;
+    SweepPair sp = {};
     const __amdgpu_buffer_rsrc_t qrs = buffer_rsrc(a.quads, a.quad_bytes);
-    uint32_t qbase = 0;
     const int n_pass = (P + kWave - 1) / kWave;
     int passes = n_pass;
     const float bound_ref = a.exact_margin ? second : best;  // complete levels change only between chunks
     for (int it = 0; it < n_pass; ++it) {
       if (lane + it * kWave < P) {
       if (iv != cur) {
-        const PairDev &pg = a.pairs[vw.pair_off + iv];
-        A0 = pg.A[0]; A1 = pg.A[1]; A2 = pg.A[2];
-        A3 = pg.A[3]; A4 = pg.A[4]; A5 = pg.A[5];
-        A6 = pg.A[6]; A7 = pg.A[7]; A8 = pg.A[8];
-        bx = pg.b[0]; by = pg.b[1]; bw = pg.b[2];
-        const ViewDev &vi = a.views[pg.i];
-        Wi = vi.W;
-        Hi = vi.H;
-        Wm1 = (float)(Wi - 1);
-        Hm1 = (float)(Hi - 1);
-        qbase = quad_base<FMT>(vi);
+        sp = pairs.at<FMT>(iv);
         cur = iv;
       }
       const PixEntry e = a.px[poff + p];
-      const float pu = (float)(e.x & 0xffffu), pv = (float)(e.x >> 16);
+      const float du = (float)((int)(e.x & 0xffffu) - pairs.ub), dv = (float)((int)(e.x >> 16) - pairs.vb);
       const float r0 = (float)(e.y & 255u), g0 = (float)((e.y >> 8) & 255u), b0 = (float)((e.y >> 16) & 255u);
-      const float ax = fmaf(A0, pu, fmaf(A1, pv, A2));
-      const float ay = fmaf(A3, pu, fmaf(A4, pv, A5));
-      const float aw = fmaf(A6, pu, fmaf(A7, pv, A8));
+      const float ax = fmaf(sp.h[0], du, fmaf(sp.h[1], dv, sp.h[2]));
+      const float ay = fmaf(sp.h[3], du, fmaf(sp.h[4], dv, sp.h[5]));
+      const float aw = fmaf(sp.h[6], du, fmaf(sp.h[7], dv, sp.h[8]));
       // every active lane in an inner view (neighbours past the 64th are
       // never taken as inner): samples without the bounds test
       if (__ballot(iv >= kWave || ((inner_views >> iv) & 1ull) == 0ull) == 0ull)
-        sample_levels<FMT, KC>(q, acc, ax, ay, aw, bx, by, bw, Wm1, Hm1, Wi, Hi, qrs, qbase, r0, g0, b0, a.T255, false);
+        sample_levels<FMT, KC>(q, acc, ax, ay, aw, sp.b[0], sp.b[1], sp.b[2], sp.f, qrs, r0, g0, b0, a.T255, false);
       else
-        sample_levels<FMT, KC>(q, acc, ax, ay, aw, bx, by, bw, Wm1, Hm1, Wi, Hi, qrs, qbase, r0, g0, b0, a.T255, true);
+        sample_levels<FMT, KC>(q, acc, ax, ay, aw, sp.b[0], sp.b[1], sp.b[2], sp.f, qrs, r0, g0, b0, a.T255, true);
       p += kWave;
       while (p >= A) {
         p -= A;
@@ -1044,8 +1147,12 @@ __device__ __forceinline__ void sweep_merge(const SweepArgs &a, const int g, con
 #endif
 constexpr int kLevelChunk = SLF_LEVEL_CHUNK;
 
+// Waves per SIMD the sweep's registers are sized for (128 VGPRs; 3 and 5
+// waves measured slower).
+constexpr int kSweepWaves = 4;
+
 template <int FMT, int KC>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a, int *__restrict__ counters) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSweepWaves))) void k_sweep(SweepArgs a, int *__restrict__ counters) {
   for_each_claimed(a.S, counters, [&](int c) { sweep_sp<FMT, KC>(a, a.order ? ro_at(a.order, c) : c); });
 }
 
@@ -1238,18 +1345,28 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
     for (int iv = 0; iv < c.N; ++iv) {
       const PairDev &pg = ro_at(a.pairs, vw.pair_off + iv);
       const ViewDev &vi = ro_at(a.views, pg.i);
-      float H[9];
+      double H[9];
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) H[3 * r + q] = (float)(pg.A_d[3 * r + q] + pg.b_d[r] * gg[q]);
+        for (int q = 0; q < 3; ++q) H[3 * r + q] = pg.A_d[3 * r + q] + pg.b_d[r] * gg[q];
+      // re-centred as in the sweep: offsets from the rounded centroid in,
+      // positions relative to the pixel nearest its projection out
+      const double hx = H[0] * c.ub + H[1] * c.vb + H[2];
+      const double hy = H[3] * c.ub + H[4] * c.vb + H[5];
+      const double hw = H[6] * c.ub + H[7] * c.vb + H[8];
+      int X0, Y0;
+      near_pixel(hx, hy, hw, vi, X0, Y0);
+      const float h0 = (float)(H[0] - X0 * H[6]), h1 = (float)(H[1] - X0 * H[7]), h2 = (float)(hx - X0 * hw);
+      const float h3 = (float)(H[3] - Y0 * H[6]), h4 = (float)(H[4] - Y0 * H[7]), h5 = (float)(hy - Y0 * hw);
+      const float h6 = (float)H[6], h7 = (float)H[7], h8 = (float)hw;
+      const SampleFrame f = frame_at<FMT>(vi, X0, Y0);
       for (int p = lane; p < c.A; p += kWave) {
         const PixEntry e = a.px[c.poff + p];
-        const float pu = (float)(e.x & 0xffffu), pv = (float)(e.x >> 16);
-        acc += tssd_sample<FMT>(fmaf(H[0], pu, fmaf(H[1], pv, H[2])), fmaf(H[3], pu, fmaf(H[4], pv, H[5])),
-                                fmaf(H[6], pu, fmaf(H[7], pv, H[8])), (float)(vi.W - 1), (float)(vi.H - 1), vi.W,
-                                vi.H, buffer_rsrc(a.quads, a.quad_bytes), quad_base<FMT>(vi), (float)(e.y & 255u),
-                                (float)((e.y >> 8) & 255u), (float)((e.y >> 16) & 255u), a.T255);
+        const float du = (float)((int)(e.x & 0xffffu) - c.ub), dv = (float)((int)(e.x >> 16) - c.vb);
+        acc += tssd_sample<FMT>(fmaf(h0, du, fmaf(h1, dv, h2)), fmaf(h3, du, fmaf(h4, dv, h5)),
+                                fmaf(h6, du, fmaf(h7, dv, h8)), f, buffer_rsrc(a.quads, a.quad_bytes),
+                                (float)(e.y & 255u), (float)((e.y >> 8) & 255u), (float)((e.y >> 16) & 255u), a.T255);
       }
     }
     views = c.N;
@@ -1867,7 +1984,7 @@ hipError_t launch_refine(int fmt, const RefineArgs &a, RefineArgs *slot, int *co
 typedef const __attribute__((address_space(4))) PoolStage ConstStage;
 
 template <int OP, int FMT, int KC>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SLF_OP_REFINE ? kRefineWaves : 1))) void k_pool(const PoolStage *__restrict__ stage_ptr, int *__restrict__ counters) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(OP == SLF_OP_REFINE ? kRefineWaves : KC <= 8 ? kSweepWaves : 1))) void k_pool(const PoolStage *__restrict__ stage_ptr, int *__restrict__ counters) {
   __shared__ WaveLds s_wave[OP == SLF_OP_REFINE ? kWavesPerBlock : 1];
   // The stage table does not change during the launch: read it through the
   // constant address space, as kernel arguments are, so that its fields are

@@ -251,6 +251,49 @@ def test_refine_lockstep_edge_cases(case):
     _lockstep(w, 2)
 
 
+def _max_side_workload(case):
+    """Views with the largest side the boundary accepts (65535 px): a wide
+    strip seen by three cameras on a horizontal line and a tall one seen by
+    three on a vertical line, 256-pixel grid cells, 40 rectangles.  The
+    cameras sit 0.0002 off the line, so that no row (column) maps exactly onto
+    the image's last one, where the inside test would be decided by rounding."""
+    from lfsynth.configs import Workload, MethodParams
+    from lfsynth.rig import View, intrinsics, pose_from_centre
+
+    W, H, gw, gh = (65535, 8, 2048, 1) if case == "wide" else (8, 65535, 1, 2048)
+    views = []
+    for i in (-1, 0, 1):
+        centre = [0.1 * i, 0.0002 * i, 0.0] if case == "wide" else [0.0002 * i, 0.1 * i, 0.0]
+        R, t = pose_from_centre(centre)
+        views.append(View(W, H, intrinsics(200.0, W, H), R, t))
+    rng = np.random.Generator(np.random.PCG64(12))
+    scene = make_scene(rng, f=200.0, W=W, H=H, sp_px=W * H / (gw * gh), n_rect=40)
+    rig = build_rig(views, scene, gw, gh, name="maxside-%s-3x%dx%d" % (case, W, H), seed=12, labels="grid")
+    return Workload(rig.name, rig, MethodParams(levels=16, iterations=1))
+
+
+@pytest.mark.parametrize("case", ["wide", "tall"])
+def test_maximum_image_side(case):
+    """The sweep and one lockstep refinement iteration on 65535 x 8 and
+    8 x 65535 views (texel rows of 65536 entries, pixel coordinates up to
+    65534 through the 24-bit index products), and a 65536-pixel side refused."""
+    from paper_1812_06856_amd import slf
+
+    _say("maximum image side, %s" % case)
+    w = _max_side_workload(case)
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    ctx.sweep()
+    _assert_clean(parity.check_sweep(orc, ctx), "sweep %s" % w.name)
+    _lockstep(w, 1, ctx=ctx, orc=orc)
+    vs = w.rig.views
+    big = slf.Context(0)
+    sides = [(v.W + (1 if case == "wide" else 0), v.H + (1 if case == "tall" else 0)) for v in vs]
+    with pytest.raises(slf.SlfError) as e:
+        big.set_cameras(sides, [v.K for v in vs], [v.R for v in vs], [v.t for v in vs])
+    assert e.value.status == slf.SLF_EUNSUPPORTED and "65535" in big.last_error()
+
+
 @pytest.mark.parametrize("mask", [1, 2, 6, 3])
 def test_refine_lockstep_term_ablations(mask):
     _say("refine lockstep term_mask %d" % mask)
