@@ -646,12 +646,12 @@ __device__ __forceinline__ float tssd_sample<SLF_FMT_F16>(float x, float y, floa
   return f16_finish(f16_fetch(x, y, w, f, quads, check), r0, g0, b0, T);
 }
 
-// levels whose texel loads are issued together (RGBA8: 4; FP16, two loads each: 2)
+// levels whose texel loads are issued together (RGBA8: 4 loads; FP16, two loads each: 8)
 #ifndef SLF_SWEEP_BATCH
 #define SLF_SWEEP_BATCH 4
 #endif
 #ifndef SLF_SWEEP_BATCH_F16
-#define SLF_SWEEP_BATCH_F16 2
+#define SLF_SWEEP_BATCH_F16 4
 #endif
 template <int KC>
 constexpr int kSweepBatchOf = KC < SLF_SWEEP_BATCH ? KC : SLF_SWEEP_BATCH;
