@@ -294,6 +294,33 @@ def test_maximum_image_side(case):
     assert e.value.status == slf.SLF_EUNSUPPORTED and "65535" in big.last_error()
 
 
+@pytest.mark.parametrize("dims", [(2, 2, 1, 1), (5, 2, 2, 1), (2, 7, 1, 3)])
+def test_minimum_image_side(dims):
+    """Views of 2 x 2, 5 x 2 and 2 x 7 pixels (the smallest side the boundary
+    accepts is 2): the sweep, two lockstep refinement iterations and the depth
+    readout against the oracle, and a 1-pixel side refused."""
+    from paper_1812_06856_amd import slf
+
+    W, H, gw, gh = dims
+    _say("minimum image side %dx%d" % (W, H))
+    w = tiny_custom(W, H, gw, gh, n_views=3, seed=21, levels=8, labels="grid", f=2.0 * max(W, H))
+    ctx = _ctx(w)
+    orc = _oracle(w)
+    ctx.sweep()
+    _assert_clean(parity.check_sweep(orc, ctx), "sweep %s" % w.name)
+    ctx, orc = _lockstep(w, 2, ctx=ctx, orc=orc)
+    planes = np.concatenate([ctx.get_planes(v)[0] for v in range(orc.V)]).astype(np.float64)
+    for v in range(orc.V):
+        D_g = ctx.get_depth(v).astype(np.float64)
+        D_o = orc.render_depth(planes, v)
+        np.testing.assert_allclose(D_g, D_o, rtol=2e-5, atol=0)
+    vs = w.rig.views
+    small = slf.Context(0)
+    with pytest.raises(slf.SlfError) as e:
+        small.set_cameras([(1, H)] * len(vs), [v.K for v in vs], [v.R for v in vs], [v.t for v in vs])
+    assert e.value.status == slf.SLF_EINVAL
+
+
 @pytest.mark.parametrize("mask", [1, 2, 6, 3])
 def test_refine_lockstep_term_ablations(mask):
     _say("refine lockstep term_mask %d" % mask)
