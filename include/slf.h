@@ -109,7 +109,10 @@ int slf_set_params(slf_ctx *ctx, const slf_params *p);
  * wh[n][2] = (W, H) with 2 <= W, H <= 65535; K[n][9], R[n][9] row-major with
  * R orthonormal (within 1e-6) and K's last row (0,0,1); t[n][3].  Resets
  * images, labels, neighbour lists (to all other views, ascending) and planes.
- * SLF_EINVAL on bad sizes or non-finite values. */
+ * SLF_EINVAL for a side below 2, a count outside [2, 4096] or non-finite
+ * values; SLF_EUNSUPPORTED for a side above 65535.  The kernels' per-sample
+ * FP32 arithmetic works on pixel offsets re-centred per superpixel (constants
+ * composed in FP64), so its accuracy does not depend on the image size. */
 int slf_set_cameras(slf_ctx *ctx, int n_views, const int32_t *wh, const double *K, const double *R,
                     const double *t);
 /* Neighbour views N(r) of view `view` used by eqs. (2) and (8); n >= 1
