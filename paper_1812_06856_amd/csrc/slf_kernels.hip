@@ -1559,27 +1559,36 @@ __device__ float energy(const RefineArgs &a, const SpCtx &c, const ViewDev &vw, 
         // bounds.  The trip counts are uniform (whole passes, then fewer than
         // kChains waves of pixels on one chain), and the wave-level counts
         // stay in scalar registers.
+        // K waves of staged pixels, one gather chain each
+        auto pass = [&](int p0, auto narrow, auto chains) {
+          constexpr int K = decltype(chains)::value;
+          Proj q[K];
+          uint32_t l[K];
+          float4 C[K];
+          float3 G[K];
+#pragma unroll
+          for (int k = 0; k < K; ++k) q[k] = staged(p0 + k * kWave + lane);
+#pragma unroll
+          for (int k = 0; k < K; ++k) l[k] = label(q[k], narrow);
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            C[k] = load_f4(tab_rs, (int)(32u * l[k]));
+            G[k] = load_f3(tab_rs, (int)(32u * l[k] + 16u));
+          }
+#pragma unroll
+          for (int k = 0; k < K; ++k) accumulate(q[k], C[k], G[k]);
+        };
         auto samples = [&](auto narrow) {
           const int n_pad = c.n_pad;
           int p0 = 0;
-          for (; p0 + kChains * kWave <= n_pad; p0 += kChains * kWave) {
-            Proj q[kChains];
-            uint32_t l[kChains];
-            float4 C[kChains];
-            float3 G[kChains];
-#pragma unroll
-            for (int k = 0; k < kChains; ++k) q[k] = staged(p0 + k * kWave + lane);
-#pragma unroll
-            for (int k = 0; k < kChains; ++k) l[k] = label(q[k], narrow);
-#pragma unroll
-            for (int k = 0; k < kChains; ++k) {
-              C[k] = load_f4(tab_rs, (int)(32u * l[k]));
-              G[k] = load_f3(tab_rs, (int)(32u * l[k] + 16u));
-            }
-#pragma unroll
-            for (int k = 0; k < kChains; ++k) accumulate(q[k], C[k], G[k]);
+          for (; p0 + kChains * kWave <= n_pad; p0 += kChains * kWave)
+            pass(p0, narrow, std::integral_constant<int, kChains>{});
+          // the staged list pads to whole waves: two waves left take two
+          // chains, one wave one
+          if (kChains > 2 && p0 + 2 * kWave <= n_pad) {
+            pass(p0, narrow, std::integral_constant<int, 2>{});
+            p0 += 2 * kWave;
           }
-          // the staged list pads to whole waves: the waves left after the whole passes take one chain
           for (; p0 < n_pad; p0 += kWave) {
             const Proj q = staged(p0 + lane);
             const uint32_t l = label(q, narrow);
