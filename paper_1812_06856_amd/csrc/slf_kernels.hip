@@ -953,7 +953,10 @@ __device__ __forceinline__ void sweep_levels(const SweepArgs &a, const int g, co
     // has q in [q_min + k0 dq, q_min + (k0 + KC) dq]: so w is smallest, and
     // the image positions (a projective map of the box, moving monotonically
     // along epipolar lines as q changes) are extreme, at the 8 corners of
-    // box x q-range.  The half-pixel margin is far above FP32 rounding.
+    // box x q-range.  The test takes absolute positions from the pair table
+    // in FP32; they and the re-centred positions the samples use differ by
+    // rounding of at most about 0.01 px at the largest image side, far below
+    // the half-pixel margin.
     bool inner = false;
     if (lane < N) {
       const PairDev &pg = a.pairs[vw.pair_off + lane];
