@@ -152,7 +152,7 @@ def cpu_baseline(w, n_sp):
                         for v, vw in enumerate(w.rig.views)])
     iters = w.params.iterations
     host = host_cpus()
-    # one thread per core of the host's CPU share: the GPU machine gives a 1-GPU job 16 cores
+    # one thread per core of the process's CPU affinity, at most 16 (a one-GPU share of the host)
     cores = max(1, min(host["affinity"], 16))
 
     def one(job):
