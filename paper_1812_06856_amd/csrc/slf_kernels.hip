@@ -289,29 +289,45 @@ __global__ __launch_bounds__(256) void k_sp_reset(const ViewDev *views, int V, i
   bbox[g] = make_int4(INT_MAX, INT_MAX, -1, -1);
 }
 
-// Each horizontal run of equal labels is counted once, by its first pixel.
-// With lab16 non-null (K <= 65536) every pixel also stores its label as 16 bits.
+// Pixel counts and bounding boxes.  One thread per pixel; the 64 pixels of
+// a wave split into runs of one label within one row, and the first lane of
+// each run adds the run's length, x range and row with atomics (integer
+// results, so their order does not matter).  A run that crosses a wave
+// boundary is added in parts.  With lab16 non-null (K <= 65536) every pixel
+// also stores its label as 16 bits.
 __global__ __launch_bounds__(256) void k_sp_count(const int *labels, uint16_t *lab16, int W, int H, int K, int sp_off,
                                                   int *count, int4 *bbox, int *err) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)W * H) return;
-  const int x = (int)(idx % W), y = (int)(idx / W);
-  const int l = labels[idx];
-  if (l < 0 || l >= K) {
-    atomicOr(err, 1);
-    return;
+  const int lane = threadIdx.x & (kWave - 1);
+  int l = -1, x = 0, y = 0;
+  if (idx < (int64_t)W * H) {
+    const uint32_t u = (uint32_t)idx;  // W H < 2^32
+    y = (int)(u / (uint32_t)W);
+    x = (int)(u - (uint32_t)y * (uint32_t)W);
+    l = labels[idx];
+    if (l < 0 || l >= K) {
+      atomicOr(err, 1);
+      l = -1;
+    } else if (lab16) {
+      lab16[idx] = (uint16_t)l;
+    }
   }
-  if (lab16) lab16[idx] = (uint16_t)l;
-  if (x > 0 && labels[idx - 1] == l) return;
-  int len = 1;
-  while (x + len < W && labels[idx + len] == l) ++len;
-  const int g = sp_off + l;
-  int *b = reinterpret_cast<int *>(bbox + g);
-  atomicAdd(count + g, len);
-  atomicMin(b + 0, x);
-  atomicMin(b + 1, y);
-  atomicMax(b + 2, x + len - 1);
-  atomicMax(b + 3, y);
+  const int left = __shfl_up(l, 1, kWave);
+  const bool valid = l >= 0;
+  const bool start = valid && (lane == 0 || x == 0 || left != l);
+  // a run ends before the next lane that starts a run or holds no valid label
+  const uint64_t brk = __ballot(start || !valid);
+  if (start) {
+    const uint64_t above = brk & ~((2ull << lane) - 1ull);
+    const int len = (above ? __ffsll((long long)above) - 1 : kWave) - lane;
+    const int g = sp_off + l;
+    int *b = reinterpret_cast<int *>(bbox + g);
+    atomicAdd(count + g, len);
+    atomicMin(b + 0, x);
+    atomicMin(b + 1, y);
+    atomicMax(b + 2, x + len - 1);
+    atomicMax(b + 3, y);
+  }
 }
 
 // Exclusive scan of count[0..S) into off[0..S], 4096 items per block.
@@ -403,25 +419,33 @@ __global__ __launch_bounds__(kBlock) void k_sp_fill(const ViewDev *views, const 
   int written = 0;
   long long sx = 0, sy = 0;
   int sr = 0, sg = 0, sb = 0;
-  for (int y = box.y; y <= box.w; ++y) {
-    for (int x0 = box.x; x0 <= box.z; x0 += kWave) {
-      const int x = x0 + lane;
-      const int64_t pidx = (int64_t)y * vw.W + x;
-      const bool m = x <= box.z && lab[(int64_t)y * vw.W + min(x, box.z)] == s;
-      const uint64_t mask = __ballot(m);
-      if (m) {
-        const int pre = __popcll(mask & ((1ull << lane) - 1ull));
-        const uint8_t *c = img + 3 * pidx;
-        const uint32_t rgba = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
-        if (written + pre < cnt) px[base + written + pre] = make_uint2((uint32_t)x | ((uint32_t)y << 16), rgba);
-        sx += x;
-        sy += y;
-        sr += c[0];
-        sg += c[1];
-        sb += c[2];
-      }
-      written += __popcll(mask);
+  // pixel (x, y) of the box, taken when `in`; the lanes of one call visit
+  // pixels in raster order, so the ballot prefix appends in raster order
+  auto visit = [&](int x, int y, bool in) {
+    const int64_t pidx = (int64_t)y * vw.W + x;
+    const bool m = in && lab[pidx] == s;
+    const uint64_t mask = __ballot(m);
+    if (m) {
+      const int pre = __popcll(mask & ((1ull << lane) - 1ull));
+      const uint8_t *c = img + 3 * pidx;
+      const uint32_t rgba = (uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16);
+      if (written + pre < cnt) px[base + written + pre] = make_uint2((uint32_t)x | ((uint32_t)y << 16), rgba);
+      sx += x;
+      sy += y;
+      sr += c[0];
+      sg += c[1];
+      sb += c[2];
     }
+    written += __popcll(mask);
+  };
+  const int bw = box.z - box.x + 1;
+  if (bw <= kWave / 2) {
+    // narrow box: several rows per pass, lane = (row, column) in raster order
+    const int rows = kWave / bw, r = lane / bw, xo = lane - r * bw;
+    for (int y0 = box.y; y0 <= box.w; y0 += rows) visit(box.x + xo, y0 + r, r < rows && y0 + r <= box.w);
+  } else {
+    for (int y = box.y; y <= box.w; ++y)
+      for (int x0 = box.x; x0 <= box.z; x0 += kWave) visit(x0 + lane, y, x0 + lane <= box.z);
   }
   sx = wave_sum_ll(sx);
   sy = wave_sum_ll(sy);
