@@ -93,6 +93,7 @@ int ensure_alloc(slf_ctx *c, size_t bytes, void **ptr) {
 void free_sp(slf_ctx *c) {
   dfree(c->d_count);
   dfree(c->d_order);
+  c->order_ok = false;
   dfree(c->d_sp_view);
   dfree(c->d_area);
   dfree(c->d_px_off);
@@ -146,6 +147,7 @@ bool views_ready(const slf_ctx *c) {
 // Per-view and per-pair geometry, composed in FP64 and rounded once.
 int build_geometry(slf_ctx *c) {
   const int V = c->V;
+  c->order_ok = false;  // the claim order follows the grids
   c->views_h.assign(V, ViewDev{});
   c->pairs_h.clear();
   int sp = 0;
@@ -347,10 +349,11 @@ int slf::ensure_setup(slf_ctx *c) {
     c->warm_ok = kept && same_cells && all_planes;
     c->lab16_ok = true;
     for (const auto &v : c->vh) c->lab16_ok = c->lab16_ok && (int64_t)v.gw * v.gh <= 65536;
-    {
-      const std::vector<int> order = strip_order(c);
-      HIP_OR_FAIL(c, hipMemcpyAsync(c->d_order, order.data(), sizeof(int) * order.size(), hipMemcpyHostToDevice,
-                                    c->stream));
+    if (!c->order_ok) {  // depends on the grids only, not on the labels: built once per geometry
+      c->order_h = strip_order(c);
+      HIP_OR_FAIL(c, hipMemcpyAsync(c->d_order, c->order_h.data(), sizeof(int) * c->order_h.size(),
+                                    hipMemcpyHostToDevice, c->stream));
+      c->order_ok = true;
     }
     HIP_OR_FAIL(c, launch_sp_build(c->d_views, c->views_h.data(), c->V, c->d_labels,
                                    c->lab16_ok ? c->d_lab16 : nullptr, c->d_rgb, c->S, c->d_count,

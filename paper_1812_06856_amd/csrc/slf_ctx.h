@@ -66,6 +66,8 @@ struct slf_ctx {
   float2 *d_centroid = nullptr;
   double2 *d_centroid_d = nullptr;
   int *d_order = nullptr;  // claim order of the per-superpixel launches (strip order, see strip_order)
+  bool order_ok = false;   // d_order holds the order of the current grids
+  std::vector<int> order_h;  // its host copy (the source of the upload, kept alive)
   float4 *d_colour = nullptr;
   slf::PixEntry *d_px = nullptr;
   float4 *d_planes[2] = {nullptr, nullptr};
