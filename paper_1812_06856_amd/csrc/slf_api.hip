@@ -362,13 +362,8 @@ int slf::ensure_setup(slf_ctx *c) {
     int herr = 0;
     HIP_OR_FAIL(c, hipMemcpyAsync(&herr, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     c->area_h.resize(c->S);
-    c->cen_h.resize(c->S);
-    c->col_h.resize(c->S);
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->col_h.data(), c->d_colour, sizeof(float4) * c->S, hipMemcpyDeviceToHost,
-                                  c->stream));
     HIP_OR_FAIL(c, hipMemcpyAsync(c->area_h.data(), c->d_area, sizeof(int) * c->S, hipMemcpyDeviceToHost, c->stream));
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->cen_h.data(), c->d_centroid_d, sizeof(double2) * c->S, hipMemcpyDeviceToHost,
-                                  c->stream));
+    c->stats_h_ok = false;  // centroids and colours are read back when a host call needs them
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     for (auto &v : c->vh) v.has_planes = false;
     if (herr & 1) {
@@ -433,6 +428,21 @@ void slf::sweep_args(const slf_ctx *c, SweepArgs &a) {
   a.choice = c->d_choice;
   a.margin = c->d_margin;
   a.work = c->d_work;
+}
+
+// Host copies of the superpixel centroids and colours (set_planes and
+// get_superpixels use them); read back once per superpixel rebuild.
+static int fetch_stats(slf_ctx *c) {
+  if (c->stats_h_ok) return SLF_OK;
+  c->cen_h.resize(c->S);
+  c->col_h.resize(c->S);
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->col_h.data(), c->d_colour, sizeof(float4) * c->S, hipMemcpyDeviceToHost,
+                                c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->cen_h.data(), c->d_centroid_d, sizeof(double2) * c->S, hipMemcpyDeviceToHost,
+                                c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  c->stats_h_ok = true;
+  return SLF_OK;
 }
 
 void slf::after_sweep(slf_ctx *c) {
@@ -762,6 +772,7 @@ int slf_set_planes(slf_ctx *c, int view, const float *planes) {
   HIP_OR_FAIL(c, hipSetDevice(c->device));
   int rc = ensure_setup(c);
   if (rc) return rc;
+  if ((rc = fetch_stats(c))) return rc;
   const ViewDev &d = c->views_h[view];
   const ViewHost &h = c->vh[view];
   const int K = d.gw * d.gh;
@@ -896,6 +907,7 @@ int slf_get_superpixels(slf_ctx *c, int view, int32_t *area, float *centroid, fl
   if (view < 0 || view >= c->V) return c->fail(SLF_EINVAL, "view %d out of range", view);
   if (c->sp_dirty || c->views_h.empty()) return c->fail(SLF_ESTATE, "superpixels not built yet");
   HIP_OR_FAIL(c, hipSetDevice(c->device));
+  if (int rc = fetch_stats(c)) return rc;
   const ViewDev &d = c->views_h[view];
   const size_t K = (size_t)d.gw * d.gh;
   if (area) std::memcpy(area, c->area_h.data() + d.sp_off, sizeof(int) * K);

@@ -96,8 +96,9 @@ struct slf_ctx {
   int64_t slic_cen_bytes = 0, slic_best_bytes = 0, slic_work_bytes = 0;
   int cur = 0;
   std::vector<int> area_h;
-  std::vector<double2> cen_h;
+  std::vector<double2> cen_h;   // centroids and colours: read back on first use after a rebuild
   std::vector<float4> col_h;
+  bool stats_h_ok = false;
   uint64_t host_evals = 0;        // sweep hypotheses (levels x non-empty superpixels)
   uint64_t host_sweep_total = 0;  // sweep px-view samples without the level bound
 
