@@ -321,6 +321,29 @@ def test_minimum_image_side(dims):
     assert e.value.status == slf.SLF_EINVAL
 
 
+def test_regridded_labels_on_one_context():
+    """One context through three grids: 20 x 15 cells, then 15 x 20 (the same
+    superpixel count, so the buffers stay and only the claim order and tables
+    must follow the new grid), then 10 x 8 (fewer superpixels), each swept and
+    checked against the oracle of that grid, then one lockstep iteration on
+    the last."""
+    import copy
+
+    _say("regridded labels on one context")
+    w = tiny_custom(160, 120, 20, 15, seed=31, levels=16, labels="grid")
+    ctx = _ctx(w)
+    for gw, gh in [(20, 15), (15, 20), (10, 8)]:
+        wk = copy.deepcopy(w)
+        for i, v in enumerate(wk.rig.views):
+            v.labels = grid_labels(v.W, v.H, gw, gh)
+            v.gw, v.gh = gw, gh
+            ctx.set_labels(i, v.labels, gw, gh)
+        orc = _oracle(wk)
+        ctx.sweep()
+        _assert_clean(parity.check_sweep(orc, ctx), "sweep on a %dx%d grid" % (gw, gh))
+    _lockstep(wk, 1, ctx=ctx, orc=orc)
+
+
 @pytest.mark.parametrize("mask", [1, 2, 6, 3])
 def test_refine_lockstep_term_ablations(mask):
     _say("refine lockstep term_mask %d" % mask)
