@@ -289,21 +289,25 @@ __global__ __launch_bounds__(256) void k_sp_reset(const ViewDev *views, int V, i
   bbox[g] = make_int4(INT_MAX, INT_MAX, -1, -1);
 }
 
-// Pixel counts and bounding boxes.  One thread per pixel; the 64 pixels of
-// a wave split into runs of one label within one row, and the first lane of
-// each run adds the run's length, x range and row with atomics (integer
-// results, so their order does not matter).  A run that crosses a wave
-// boundary is added in parts.  With lab16 non-null (K <= 65536) every pixel
-// also stores its label as 16 bits.
+// Pixel counts and bounding boxes.  One wave per tile of 16 x 4 pixels
+// (lane = 16 row + column): for each distinct label of the tile, one lane
+// adds the label's pixel count, column range and row range there, all read
+// off the ballot mask of its pixels, with integer atomics (their order does
+// not matter).  With lab16 non-null (K <= 65536) every pixel also stores its
+// label as 16 bits.
+constexpr int kCountTileW = 16, kCountTileH = kWave / kCountTileW;
 __global__ __launch_bounds__(256) void k_sp_count(const int *labels, uint16_t *lab16, int W, int H, int K, int sp_off,
                                                   int *count, int4 *bbox, int *err) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
-  int l = -1, x = 0, y = 0;
-  if (idx < (int64_t)W * H) {
-    const uint32_t u = (uint32_t)idx;  // W H < 2^32
-    y = (int)(u / (uint32_t)W);
-    x = (int)(u - (uint32_t)y * (uint32_t)W);
+  const int tiles_x = (W + kCountTileW - 1) / kCountTileW;
+  const int tiles = tiles_x * ((H + kCountTileH - 1) / kCountTileH);
+  const int tile = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  if (tile >= tiles) return;  // the whole wave
+  const int x0 = (tile % tiles_x) * kCountTileW, y0 = (tile / tiles_x) * kCountTileH;
+  const int x = x0 + (lane & (kCountTileW - 1)), y = y0 + lane / kCountTileW;
+  int l = -1;
+  if (x < W && y < H) {
+    const int64_t idx = (int64_t)y * W + x;
     l = labels[idx];
     if (l < 0 || l >= K) {
       atomicOr(err, 1);
@@ -312,21 +316,28 @@ __global__ __launch_bounds__(256) void k_sp_count(const int *labels, uint16_t *l
       lab16[idx] = (uint16_t)l;
     }
   }
-  const int left = __shfl_up(l, 1, kWave);
-  const bool valid = l >= 0;
-  const bool start = valid && (lane == 0 || x == 0 || left != l);
-  // a run ends before the next lane that starts a run or holds no valid label
-  const uint64_t brk = __ballot(start || !valid);
-  if (start) {
-    const uint64_t above = brk & ~((2ull << lane) - 1ull);
-    const int len = (above ? __ffsll((long long)above) - 1 : kWave) - lane;
-    const int g = sp_off + l;
-    int *b = reinterpret_cast<int *>(bbox + g);
-    atomicAdd(count + g, len);
-    atomicMin(b + 0, x);
-    atomicMin(b + 1, y);
-    atomicMax(b + 2, x + len - 1);
-    atomicMax(b + 3, y);
+  uint64_t pending = __ballot(l >= 0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int L = __shfl(l, leader, kWave);
+    const uint64_t same = __ballot(l == L);
+    pending &= ~same;
+    if (lane == leader) {
+      const uint32_t cols = (uint32_t)((same | same >> 16 | same >> 32 | same >> 48) & 0xffffu);
+      int ylo = kCountTileH, yhi = -1;
+      for (int r = 0; r < kCountTileH; ++r)
+        if ((same >> (kCountTileW * r)) & 0xffffull) {
+          ylo = min(ylo, r);
+          yhi = r;
+        }
+      const int g = sp_off + L;
+      int *b = reinterpret_cast<int *>(bbox + g);
+      atomicAdd(count + g, __popcll(same));
+      atomicMin(b + 0, x0 + __ffs(cols) - 1);
+      atomicMin(b + 1, y0 + ylo);
+      atomicMax(b + 2, x0 + 31 - __clz(cols));
+      atomicMax(b + 3, y0 + yhi);
+    }
   }
 }
 
@@ -471,8 +482,8 @@ hipError_t launch_sp_build(const ViewDev *views_d, const ViewDev *views_h, int V
   hipLaunchKernelGGL(k_sp_reset, dim3((S + 255) / 256), dim3(256), 0, st, views_d, V, S, count, bbox, sp_view, err);
   for (int v = 0; v < V; ++v) {
     const ViewDev &vw = views_h[v];
-    const int64_t n = (int64_t)vw.W * vw.H;
-    hipLaunchKernelGGL(k_sp_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, labels + vw.pix_off,
+    const int64_t tiles = (int64_t)((vw.W + kCountTileW - 1) / kCountTileW) * ((vw.H + kCountTileH - 1) / kCountTileH);
+    hipLaunchKernelGGL(k_sp_count, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, labels + vw.pix_off,
                        lab16 ? lab16 + vw.pix_off : nullptr, vw.W, vw.H, vw.gw * vw.gh, vw.sp_off, count, bbox, err);
   }
   const int per = kScanThreads * kScanItems;
