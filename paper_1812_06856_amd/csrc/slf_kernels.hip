@@ -1196,10 +1196,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kSweepWa
 
 // Writes one launch's arguments into device memory (the launch copies its
 // own arguments, so no host buffer has to outlive the call; stream order
-// puts the write after every earlier kernel and before the one that reads).
+// puts the write after every earlier kernel and before the one that reads)
+// and clears the claim counters of the launch that follows.
 template <class T>
-__global__ void k_put_args(T *dst, T v) {
+__global__ void k_put_args_reset(T *dst, T v, int *counters) {
   if (threadIdx.x == 0) *dst = v;
+  if (threadIdx.x < kPoolQueues) counters[threadIdx.x * kPoolCounterStride] = 0;
 }
 
 hipError_t launch_sweep(int fmt, const SweepArgs &a, int *counters, int n_cu, hipStream_t st) {
@@ -2014,8 +2016,7 @@ hipError_t launch_refine(int fmt, const RefineArgs &a, RefineArgs *slot, int *co
   const void *k = fmt == SLF_FMT_U8    ? (const void *)k_refine<SLF_FMT_U8>
                   : fmt == SLF_FMT_F16 ? (const void *)k_refine<SLF_FMT_F16>
                                        : (const void *)k_refine<SLF_FMT_F32>;
-  hipLaunchKernelGGL(k_put_args<RefineArgs>, dim3(1), dim3(64), 0, st, slot, a);
-  hipLaunchKernelGGL(k_pool_reset, dim3(1), dim3(64), 0, st, counters);
+  hipLaunchKernelGGL(k_put_args_reset<RefineArgs>, dim3(1), dim3(64), 0, st, slot, a, counters);
   const RefineArgs *args = slot;
   void *kargs[] = {(void *)&args, (void *)&counters};
   return hipLaunchKernel(k, dim3(persistent_blocks(k, n_cu, a.S)), dim3(kBlock), kargs, 0, st);
