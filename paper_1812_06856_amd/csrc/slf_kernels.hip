@@ -449,14 +449,20 @@ __global__ __launch_bounds__(kBlock) void k_sp_fill(const ViewDev *views, const 
     }
     written += __popcll(mask);
   };
+  // the box as one raster sequence of bw bh pixels, 64 per pass: lane j of
+  // a pass takes pixel i0 + j at (xo, yo), advanced by 64 pixels each pass
   const int bw = box.z - box.x + 1;
-  if (bw <= kWave / 2) {
-    // narrow box: several rows per pass, lane = (row, column) in raster order
-    const int rows = kWave / bw, r = lane / bw, xo = lane - r * bw;
-    for (int y0 = box.y; y0 <= box.w; y0 += rows) visit(box.x + xo, y0 + r, r < rows && y0 + r <= box.w);
-  } else {
-    for (int y = box.y; y <= box.w; ++y)
-      for (int x0 = box.x; x0 <= box.z; x0 += kWave) visit(x0 + lane, y, x0 + lane <= box.z);
+  const int64_t n = (int64_t)bw * (box.w - box.y + 1);
+  const int dq = kWave / bw, dr = kWave % bw;
+  int xo = lane % bw, yo = lane / bw;
+  for (int64_t i0 = 0; i0 < n; i0 += kWave) {
+    visit(box.x + xo, box.y + yo, i0 + lane < n);
+    xo += dr;
+    yo += dq;
+    if (xo >= bw) {  // xo < 2 bw here
+      xo -= bw;
+      ++yo;
+    }
   }
   sx = wave_sum_ll(sx);
   sy = wave_sum_ll(sy);
