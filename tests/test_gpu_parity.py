@@ -272,16 +272,18 @@ def _max_side_workload(case):
     return Workload(rig.name, rig, MethodParams(levels=16, iterations=1))
 
 
-@pytest.mark.parametrize("case", ["wide", "tall"])
-def test_maximum_image_side(case):
+@pytest.mark.parametrize("case,storage", [("wide", "u8"), ("tall", "u8"), ("wide", "f16"), ("wide", "f32")])
+def test_maximum_image_side(case, storage):
     """The sweep and one lockstep refinement iteration on 65535 x 8 and
     8 x 65535 views (texel rows of 65536 entries, pixel coordinates up to
-    65534 through the 24-bit index products), and a 65536-pixel side refused."""
+    65534 through the 24-bit index products), with each texel storage form,
+    and a 65536-pixel side refused."""
     from paper_1812_06856_amd import slf
 
-    _say("maximum image side, %s" % case)
+    _say("maximum image side, %s, %s texels" % (case, storage))
     w = _max_side_workload(case)
-    ctx = _ctx(w)
+    fmt = {"u8": slf.SLF_IMAGE_U8, "f16": slf.SLF_IMAGE_F16, "f32": slf.SLF_IMAGE_F32}[storage]
+    ctx = _ctx(w, image_precision=fmt)
     orc = _oracle(w)
     ctx.sweep()
     _assert_clean(parity.check_sweep(orc, ctx), "sweep %s" % w.name)
